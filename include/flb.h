@@ -1,0 +1,231 @@
+/*
+ * flb.h — C ABI of libflb: the fluctuating D2Q9 lattice-Boltzmann step in the
+ * velocity-dependent f-norm moment basis on AMD MI355X (gfx950).
+ *
+ * Method: Kaehler & Wagner, "A fluctuating lattice-Boltzmann method with
+ * improved Galilean invariance".
+ *   - update: Sec. II, eq. (1) (stream) and eq. (6) (collision in moment
+ *     space, Lambda^{ab} = -delta^{ab}/tau^a, unit Gaussian N per mode);
+ *   - noise amplitude: eq. (20), xi^a = sqrt(mu rho (2 tau^a - 1)) / tau^a,
+ *     with the noise strength mu = kT / theta = 3 kT (the paper's unit-mass
+ *     Poisson gas is mu = 1);
+ *   - moment basis: Sec. IV, Gram-Schmidt of the Hermite rows of eq. (A3)
+ *     under sum_i a_i f_i^0(1,u) b_i at the local velocity (eqs. (27)-(32)),
+ *     or the fixed Hermite basis of App. A, or the basis at the nearest point
+ *     of the 51 x 51 velocity grid of Sec. IV (table variant);
+ *   - observables: correlators <df_i df_j> (eq. (16)) and moment correlators
+ *     (eq. (23)) in the f-norm at (rho0, u0) (Sec. IV, after eq. (34)) and in
+ *     the Hermite norm; structure factors, eqs. (24)-(26).
+ *
+ * Conventions (all entry points):
+ *   - Return 0 (FLB_OK) or a negative FLB_E_* code; flb_last_error() gives a
+ *     thread-local message for the last failure on the calling thread.
+ *   - Lattices are periodic nx x ny, velocities ordered as the columns of
+ *     eq. (A3): (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1).
+ *   - Host arrays of populations or moments are FP64, structure of arrays
+ *     [9][ny][nx] (index a*nx*ny + y*nx + x), unshifted f, whatever the
+ *     storage precision.  Per-site fields are [ny][nx].  Callers own every
+ *     host buffer; the library owns handles and, except with *_create_on,
+ *     the device memory behind them.
+ *   - Work is enqueued on the stream given at creation (a hipStream_t; NULL
+ *     means a library-created non-blocking stream).  step() only enqueues;
+ *     read_*, sync and checkpoint synchronise the stream and report device
+ *     errors found so far.  Handles are not thread-safe; the server is.
+ */
+#ifndef FLB_H
+#define FLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FLB_OK = 0,
+  FLB_E_ARG = -1,              /* invalid argument (sizes, tau <= 1/2, kT < 0, ...) */
+  FLB_E_OOM = -2,              /* device or host allocation failed                 */
+  FLB_E_HIP = -3,              /* HIP runtime error                                */
+  FLB_E_INVALID_VELOCITY = -4, /* some f_i^0(1,u) <= 0: no f-norm basis (Fig. 11)  */
+  FLB_E_NONFINITE = -5,        /* density <= 0 or a non-finite population          */
+  FLB_E_ADMISSION = -6,        /* server: request can never fit / queue closed     */
+  FLB_E_STATE = -7             /* call not valid in the handle's current state     */
+};
+
+typedef enum { FLB_FP64 = 0, FLB_FP32_SHIFTED = 1 } flb_precision;
+typedef enum {
+  FLB_BASIS_FNORM_LOCAL = 0, /* Sec. IV, exact local f-norm basis          */
+  FLB_BASIS_HERMITE = 1,     /* App. A, Hermite norm (velocity independent) */
+  FLB_BASIS_FNORM_LUT = 2    /* Sec. IV, basis at the nearest grid velocity */
+} flb_basis;
+typedef enum { FLB_INIT_EQUILIBRIUM = 0, FLB_INIT_THERMAL = 1, FLB_INIT_FIELDS = 2 } flb_init;
+typedef enum { FLB_AT_LOCAL = 0, FLB_AT_U0 = 1, FLB_AT_HERMITE = 2 } flb_moment_basis;
+typedef enum {
+  FLB_SK_RHO = 0, FLB_SK_JX = 1, FLB_SK_JY = 2, FLB_SK_JXJY_RE = 3, FLB_SK_JXJY_IM = 4
+} flb_sk_field;
+
+/* Parameters of one lattice. */
+typedef struct {
+  int32_t nx, ny;       /* periodic sides, each >= 3                              */
+  double rho0;          /* reference density (> 0); FP32 storage keeps f - w rho0  */
+  double ux0, uy0;      /* background velocity (inside the validity region)       */
+  double kT;            /* noise temperature (>= 0); mu = 3 kT                    */
+  double tau[6];        /* relaxation times of modes 3..8 (Pi_xx-yy, Pi_xy,
+                           Pi_xx+yy, q_x, q_y, eps), each > 1/2                   */
+  uint64_t seed;        /* Philox key: noise is keyed by (seed, step, site)       */
+  int32_t precision;    /* flb_precision                                          */
+  int32_t basis;        /* flb_basis                                              */
+  int32_t init;         /* flb_init: EQUILIBRIUM f^0(rho0,u0); THERMAL adds ideal-
+                           gas fluctuations sqrt(mu f^0) N; FIELDS waits for
+                           flb_lattice_set_fields                                 */
+  int32_t sample_every; /* correlator sample every n steps (0: off)               */
+  int32_t sk_every;     /* structure-factor sample every n steps (0: off)         */
+  int32_t block_steps;  /* samples per time block for standard errors (0: none)   */
+} flb_params;
+
+/* Correlators of df = f - f^0(rho0, u0) over all (site, sample) pairs. */
+typedef struct {
+  uint64_t nsamples;          /* site-samples                                     */
+  uint64_t nblocks;           /* closed time blocks behind the standard errors    */
+  double mean_df[9];          /* <f_i> - f_i^0(rho0, u0)                          */
+  double cov_f[81];           /* <df_i df_j>, centred on the sample mean          */
+  double cov_m_fnorm_u0[81];  /* m~(u0) C m~(u0)^T, f-norm at (rho0,u0), eq. (23) */
+  double cov_m_hermite[81];   /* m C m^T, Hermite rows of eq. (A3)                */
+  double se_cov_f[81];        /* standard errors from the time blocks (NaN if < 2)*/
+  double se_cov_m[81];        /* same for cov_m_fnorm_u0                          */
+} flb_cov;
+
+typedef struct flb_lattice flb_lattice;
+
+/* Creates a lattice, allocates its device memory and initialises the
+ * populations per p->init.  hip_stream: hipStream_t or NULL. */
+int flb_lattice_create(const flb_params* p, void* hip_stream, flb_lattice** out);
+
+/* Device bytes a lattice with these parameters needs (for create_on). */
+size_t flb_lattice_bytes(const flb_params* p);
+
+/* As create, but all device arrays are carved from the caller's buffer
+ * dev_buf of `bytes` >= flb_lattice_bytes(p) (e.g. a torch tensor); the
+ * caller keeps ownership and must outlive the handle. */
+int flb_lattice_create_on(const flb_params* p, void* dev_buf, size_t bytes, void* hip_stream,
+                          flb_lattice** out);
+
+/* f = f^0(rho(x), u(x)) per site (eq. (A1)); host arrays [ny][nx]. */
+int flb_lattice_set_fields(flb_lattice* L, const double* rho, const double* ux, const double* uy);
+
+/* Replace the populations (host [9][ny][nx], unshifted) and set the time. */
+int flb_lattice_set_populations(flb_lattice* L, const double* f, uint64_t t);
+
+/* Enqueue nsteps updates (collision, stream, sampling when due). */
+int flb_lattice_step(flb_lattice* L, uint64_t nsteps);
+
+/* Wait for the stream; returns the first device error (FLB_E_INVALID_VELOCITY
+ * or FLB_E_NONFINITE) raised since creation, with flb_lattice_error_step()
+ * naming the step. */
+int flb_lattice_sync(flb_lattice* L);
+
+int flb_lattice_read_populations(flb_lattice* L, double* f);
+/* Moments per site in basis `at` (flb_moment_basis); host [9][ny][nx]. */
+int flb_lattice_read_moments(flb_lattice* L, int32_t at, double* m);
+int flb_lattice_read_covariance(flb_lattice* L, flb_cov* out);
+/* <|dA(k)|^2> / (nx ny) (which = RHO, JX, JY) or <dj~_x(k) dj~_y(-k)> / (nx ny)
+ * (real, imaginary part), k = 2 pi (kx/nx, ky/ny), host [ky][kx]. */
+int flb_lattice_read_structure_factor(flb_lattice* L, int32_t which, double* out);
+/* sum_x dA(x) exp(-i k.x) of the current state, which = 0 rho, 1 j~_x, 2 j~_y. */
+int flb_lattice_read_fourier_mode(flb_lattice* L, int32_t which, int32_t kx, int32_t ky,
+                                  double out[2]);
+int flb_lattice_reset_stats(flb_lattice* L);
+
+/* Checkpoint: exact storage bits plus time and parameters; restoring into a
+ * lattice with the same parameters continues bit-identically (the noise is
+ * keyed by the step).  Statistics are not part of the checkpoint. */
+size_t flb_lattice_checkpoint_bytes(flb_lattice* L);
+int flb_lattice_checkpoint(flb_lattice* L, void* host, size_t bytes);
+int flb_lattice_restore(flb_lattice* L, const void* host, size_t bytes);
+
+uint64_t flb_lattice_time(flb_lattice* L);
+int64_t flb_lattice_error_step(flb_lattice* L); /* -1 when no error */
+
+/* Device time of the step kernels enqueued since the last reset, measured
+ * with HIP events around each launch (enable first; adds two events per
+ * launch). */
+int flb_lattice_profile(flb_lattice* L, int32_t on);
+int flb_lattice_kernel_time(flb_lattice* L, double* ms, uint64_t* launches);
+
+void flb_lattice_destroy(flb_lattice* L);
+const char* flb_last_error(void);
+
+/* ------------------------------------------------------------- ensembles
+ * n replicas of one lattice shape (same nx, ny, precision, basis), each with
+ * its own rho0, u0, kT, tau, seed and sampling, advanced by one batched
+ * kernel launch per step; chunks of steps are replayed from a captured
+ * hipGraph.  Replica results are bit-identical to running each alone. */
+typedef struct flb_ensemble flb_ensemble;
+int flb_ensemble_create(const flb_params* per_replica, int32_t n, void* hip_stream,
+                        flb_ensemble** out);
+/* Graph chunk length (steps per captured graph), 0 = launch eagerly. */
+int flb_ensemble_set_graph_chunk(flb_ensemble* E, int32_t steps);
+int flb_ensemble_step(flb_ensemble* E, uint64_t nsteps);
+int flb_ensemble_sync(flb_ensemble* E);
+int flb_ensemble_read_populations(flb_ensemble* E, int32_t i, double* f);
+int flb_ensemble_read_covariance(flb_ensemble* E, int32_t i, flb_cov* out);
+uint64_t flb_ensemble_time(flb_ensemble* E);
+/* Device time of the step launches (graph replays count one launch per step). */
+int flb_ensemble_profile(flb_ensemble* E, int32_t on);
+int flb_ensemble_kernel_time(flb_ensemble* E, double* ms, uint64_t* launches);
+void flb_ensemble_destroy(flb_ensemble* E);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of simulation requests of mixed size, temperature and
+ * background velocity.  Requests wait in FIFO order; one is admitted as soon
+ * as a slot is free and its device footprint fits the memory budget; all
+ * admitted requests advance together, one batched launch per step, in
+ * chunks of `chunk_steps`; finished requests leave at chunk boundaries and
+ * free their slot and memory for the next.  A request's result equals the
+ * result of running it alone (noise keyed by its own seed, step and site;
+ * per-request reduction order). */
+typedef struct {
+  size_t mem_budget_bytes; /* device bytes for admitted lattices                   */
+  int32_t max_slots;       /* concurrent requests                                  */
+  int32_t chunk_steps;     /* steps between admission points                       */
+  int32_t precision;       /* storage of every request (flb_precision)             */
+  int32_t basis;           /* basis of every request (flb_basis)                   */
+  int32_t threaded;        /* 1: a worker thread drives the GPU; 0: flb_server_pump */
+} flb_server_config;
+
+typedef struct {
+  flb_params p;            /* p.precision / p.basis are taken from the config      */
+  uint64_t nsteps;
+  uint64_t tag;            /* caller's id, returned with the result                */
+} flb_request;
+
+typedef struct {
+  uint64_t id, tag;
+  int32_t status;          /* FLB_OK or an error code                              */
+  int32_t pad_;
+  uint64_t nsteps;
+  double t_submit, t_admit, t_done;  /* seconds on the server clock              */
+  flb_cov cov;
+} flb_result;
+
+typedef struct flb_server flb_server;
+int flb_server_create(const flb_server_config* cfg, void* hip_stream, flb_server** out);
+/* Device bytes a request occupies while admitted. */
+size_t flb_server_request_bytes(const flb_request* r);
+int flb_server_submit(flb_server* S, const flb_request* r, uint64_t* id);
+/* Non-threaded servers: run up to max_chunks chunks (admit, step, retire). */
+int flb_server_pump(flb_server* S, int32_t max_chunks, int32_t* did_work);
+/* Completed results, oldest first; *n = number written (<= max). */
+int flb_server_poll(flb_server* S, flb_result* out, int32_t max, int32_t* n);
+/* Block until every submitted request has completed. */
+int flb_server_drain(flb_server* S);
+/* Queue lengths and device-busy statistics. */
+int flb_server_stats(flb_server* S, int32_t* queued, int32_t* active, uint64_t* completed,
+                     double* busy_seconds, double* wall_seconds);
+void flb_server_destroy(flb_server* S);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,375 @@
+// flb_device.hpp — per-site arithmetic of the fluctuating D2Q9 step on gfx950.
+//
+// Kaehler & Wagner, "A fluctuating lattice-Boltzmann method with improved
+// Galilean invariance": the update of Sec. II, eq. (6), with the
+// velocity-dependent f-norm moment basis of Sec. IV (eqs. (27)-(32)), the
+// fixed Hermite basis of App. A, or the grid-velocity (table) variant of
+// Sec. IV, plus the FDT noise amplitude of eq. (20).
+//
+// Design (not the paper's): the Gram-Schmidt of the nine Hermite rows
+// under <a,b>_g = sum_i a_i g_i b_i, g = f^0(1,u), is carried out in closed
+// form.  The three conserved rows are 1, sqrt3 (v_x - u_x), sqrt3 (v_y - u_y)
+// exactly; the six others follow from the Cholesky factor L of the 6x6
+// Schur complement G' = G - P P^T of the Hermite Gram matrix, whose entries
+// are quadratic polynomials in u (G) and the projections P of the Hermite
+// rows on the conserved rows (cubic).  Classical Gram-Schmidt with positive
+// normalisation is exactly m~^{3..8} = L^-1 (m^{3..8} - projections), so
+//   M~^{3..8} = L^-1 d,  d = Hermite non-equilibrium moments M - M^0(rho,u),
+//   df = D_g p^T L^-T dM~.
+// Nothing is tabulated and no 9x9 product is formed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "flb_kernels.hpp"
+
+namespace flb {
+
+// D2Q9 velocity set (Fig. 1; order of the columns of eqs. (A3)/(A4)).
+constexpr int kVX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kVY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+enum : int { kBasisFnormLocal = 0, kBasisHermite = 1, kBasisFnormLut = 2 };
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 products, word shuffle, key xor; key bumped by the Weyl
+// increments between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Six unit Gaussians for one (site, step, tag): the 128 Philox bits give six
+// 21-bit integers (top 21 bits of each word, then the low 11 bits of words
+// 0/2 joined with the low 10 bits of words 1/3); u = (U + 1/2) 2^-21 and
+// Box-Muller on the pairs (u0,u1), (u2,u3), (u4,u5).
+template <typename R>
+__device__ __forceinline__ void box_muller(uint32_t ua, uint32_t ub, R& n0, R& n1);
+
+template <>
+__device__ __forceinline__ void box_muller<float>(uint32_t ua, uint32_t ub, float& n0,
+                                                  float& n1) {
+  const float fa = __fmaf_rn((float)ua, 4.76837158203125e-07f, 2.384185791015625e-07f);
+  const float fb = __fmaf_rn((float)ub, 9.5367431640625e-07f, 4.76837158203125e-07f);  // 2u
+  const float r = sqrtf(-2.0f * logf(fa));
+  float s, c;
+  sincospif(fb, &s, &c);
+  n0 = r * c;
+  n1 = r * s;
+}
+
+template <>
+__device__ __forceinline__ void box_muller<double>(uint32_t ua, uint32_t ub, double& n0,
+                                                   double& n1) {
+  const double fa = ((double)ua + 0.5) * 4.76837158203125e-07;
+  const double fb = ((double)ub + 0.5) * 9.5367431640625e-07;  // 2u
+  const double r = sqrt(-2.0 * log(fa));
+  double s, c;
+  sincospi(fb, &s, &c);
+  n0 = r * c;
+  n1 = r * s;
+}
+
+template <typename R>
+__device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint64_t site,
+                                               uint64_t step, uint32_t tag, R N[6]) {
+  const uint4 w = philox4x32_10(
+      make_uint4((uint32_t)site, (uint32_t)(site >> 32), (uint32_t)step,
+                 (uint32_t)(step >> 32) ^ tag),
+      k0, k1);
+  const uint32_t u4 = (w.x & 0x7FFu) | ((w.y & 0x3FFu) << 11);
+  const uint32_t u5 = (w.z & 0x7FFu) | ((w.w & 0x3FFu) << 11);
+  box_muller<R>(w.x >> 11, w.y >> 11, N[0], N[1]);
+  box_muller<R>(w.z >> 11, w.w >> 11, N[2], N[3]);
+  box_muller<R>(u4, u5, N[4], N[5]);
+}
+
+__device__ __forceinline__ float rsqrt_t(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcp_t(float x) { return __frcp_rn(x); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+
+// Per-lattice constants of the collision, in the compute type.
+template <typename R>
+struct CollideConst {
+  R rho0;
+  R rt[6];     // 1/tau^a, a = 3..8
+  R xc[6];     // sqrt(mu (2 tau^a - 1)) / tau^a: xi^a = sqrt(rho) xc^a (eq. (20))
+  uint32_t k0, k1;
+  int noise;   // 0 when kT == 0
+};
+
+// Hermite moments of the shifted populations h_i = f_i - w_i rho0 (the shift
+// carries no mass-free moment: sum_i m_i^a w_i = delta^a0, eq. (22)).
+template <typename R>
+struct Moments {
+  R drho, jx, jy;  // rho - rho0, j
+  R M3, M4, M5, M6, M7, M8;
+};
+
+template <typename R>
+__device__ __forceinline__ Moments<R> hermite_moments(const R h[9]) {
+  constexpr R S32 = R(1.2247448713915890491);  // sqrt(3/2)
+  Moments<R> m;
+  const R a13 = h[1] + h[3], a24 = h[2] + h[4];
+  const R d13 = h[1] - h[3], d24 = h[2] - h[4];
+  const R p57 = h[5] + h[7], p68 = h[6] + h[8];
+  const R m57 = h[5] - h[7], m68 = h[6] - h[8];
+  const R s58 = p57 + p68;
+  const R dx = m57 - m68;   // h5 - h6 - h7 + h8
+  const R dy = m57 + m68;   // h5 + h6 - h7 - h8
+  const R dxy = p57 - p68;  // h5 - h6 + h7 - h8
+  const R axis = a13 + a24;
+  m.drho = (h[0] + axis) + s58;
+  m.jx = d13 + dx;
+  m.jy = d24 + dy;
+  m.M3 = R(1.5) * (a13 - a24);
+  m.M4 = R(3) * dxy;
+  m.M5 = (R(0.5) * axis - h[0]) + R(2) * s58;
+  m.M6 = S32 * (R(2) * dx - d13);
+  m.M7 = S32 * (R(2) * dy - d24);
+  m.M8 = (R(0.5) * h[0] - axis) + R(2) * s58;
+  return m;
+}
+
+// sigma_i = sum_{a=3..8} m_i^a Y_a for the Hermite rows of eq. (A3).
+template <typename R>
+__device__ __forceinline__ void hermite_back(const R Y[6], R s[9]) {
+  constexpr R S32 = R(1.2247448713915890491), S6 = R(2.4494897427831780982);
+  const R base = R(0.5) * Y[2] - Y[5];
+  const R t3 = R(1.5) * Y[0];
+  const R q6 = S32 * Y[3], q7 = S32 * Y[4];
+  s[0] = R(0.5) * Y[5] - Y[2];
+  s[1] = (base + t3) - q6;
+  s[3] = (base + t3) + q6;
+  s[2] = (base - t3) - q7;
+  s[4] = (base - t3) + q7;
+  const R db = R(2) * (Y[2] + Y[5]);
+  const R e = R(3) * Y[1];
+  const R p6 = S6 * Y[3], p7 = S6 * Y[4];
+  const R dp = db + e, dm = db - e;
+  s[5] = dp + (p6 + p7);
+  s[7] = dp - (p6 + p7);
+  s[6] = dm - (p6 - p7);
+  s[8] = dm + (p6 - p7);
+}
+
+// g_i = f_i^0(1, u) of eq. (A1).
+template <typename R>
+__device__ __forceinline__ void unit_equilibrium(R bx, R by, R g[9]) {
+  const R xx = bx * bx, yy = by * by;
+  const R base = R(1) - R(1.5) * (xx + yy);
+  const R c5 = bx + by, c6 = by - bx;
+  const R ax = base + R(4.5) * xx, ay = base + R(4.5) * yy;
+  const R d5 = base + R(4.5) * c5 * c5, d6 = base + R(4.5) * c6 * c6;
+  g[0] = R(4.0 / 9.0) * base;
+  g[1] = R(1.0 / 9.0) * (ax + R(3) * bx);
+  g[3] = R(1.0 / 9.0) * (ax - R(3) * bx);
+  g[2] = R(1.0 / 9.0) * (ay + R(3) * by);
+  g[4] = R(1.0 / 9.0) * (ay - R(3) * by);
+  g[5] = R(1.0 / 36.0) * (d5 + R(3) * c5);
+  g[7] = R(1.0 / 36.0) * (d5 - R(3) * c5);
+  g[6] = R(1.0 / 36.0) * (d6 + R(3) * c6);
+  g[8] = R(1.0 / 36.0) * (d6 - R(3) * c6);
+}
+
+// Local f-norm factors at basis velocity (bx, by): inverse pivots r[6] and
+// strict lower part of the Cholesky factor of the Schur complement, plus the
+// conserved-row projections P0, P1, P2 of Hermite rows 3..7 (row 8 has none).
+template <typename R>
+struct Basis {
+  R r[6];
+  R L[15];  // L10 L20 L21 L30 L31 L32 L40 L41 L42 L43 L50 L51 L52 L53 L54
+  R P0[3];            // rows 3,4,5
+  R P1[5], P2[5];     // rows 3..7
+};
+
+template <typename R>
+__device__ __forceinline__ void fnorm_basis(R bx, R by, Basis<R>& B) {
+  constexpr R S3 = R(1.7320508075688772935), S6 = R(2.4494897427831780982);
+  constexpr R H6 = R(1.2247448713915890491);  // sqrt6 / 2
+  constexpr R T2 = R(2.1213203435596425732);  // 3 / sqrt2
+  const R xx = bx * bx, yy = by * by, xy = bx * by, uu = xx + yy, dd = xx - yy;
+  // conserved-row projections <1, m^a>_g, <m~^1, m^a>_g, <m~^2, m^a>_g
+  const R P03 = R(1.5) * dd, P04 = R(3) * xy, P05 = R(1.5) * uu;
+  B.P0[0] = P03; B.P0[1] = P04; B.P0[2] = P05;
+  B.P1[0] = S3 * bx * (R(1) - P03);
+  B.P1[1] = S3 * by * (R(1) - R(3) * xx);
+  B.P1[2] = S3 * bx * (R(1) - P05);
+  B.P1[3] = T2 * yy;
+  B.P1[4] = R(2) * T2 * xy;
+  B.P2[0] = -S3 * by * (R(1) + P03);
+  B.P2[1] = S3 * bx * (R(1) - R(3) * yy);
+  B.P2[2] = S3 * by * (R(1) - P05);
+  B.P2[3] = R(2) * T2 * xy;
+  B.P2[4] = T2 * xx;
+  const R* p1 = B.P1;
+  const R* p2 = B.P2;
+  // Hermite Gram matrix under g minus the conserved projections (lower part).
+  const R A00 = (R(1) + R(0.75) * uu) - (P03 * P03 + p1[0] * p1[0] + p2[0] * p2[0]);
+  const R A10 = -(P04 * P03 + p1[1] * p1[0] + p2[1] * p2[0]);
+  const R A11 = (R(1) + R(3) * uu) - (P04 * P04 + p1[1] * p1[1] + p2[1] * p2[1]);
+  const R A20 = R(0.75) * dd - (P05 * P03 + p1[2] * p1[0] + p2[2] * p2[0]);
+  const R A21 = R(6) * xy - (P05 * P04 + p1[2] * p1[1] + p2[2] * p2[1]);
+  const R A22 = (R(1) + R(0.75) * uu) - (P05 * P05 + p1[2] * p1[2] + p2[2] * p2[2]);
+  const R A30 = -H6 * bx - (p1[3] * p1[0] + p2[3] * p2[0]);
+  const R A31 = S6 * by - (p1[3] * p1[1] + p2[3] * p2[1]);
+  const R A32 = H6 * bx - (p1[3] * p1[2] + p2[3] * p2[2]);
+  const R A33 = (R(1) + R(3) * xx + R(1.5) * yy) - (p1[3] * p1[3] + p2[3] * p2[3]);
+  const R A40 = H6 * by - (p1[4] * p1[0] + p2[4] * p2[0]);
+  const R A41 = S6 * bx - (p1[4] * p1[1] + p2[4] * p2[1]);
+  const R A42 = H6 * by - (p1[4] * p1[2] + p2[4] * p2[2]);
+  const R A43 = R(6) * xy - (p1[4] * p1[3] + p2[4] * p2[3]);
+  const R A44 = (R(1) + R(1.5) * xx + R(3) * yy) - (p1[4] * p1[4] + p2[4] * p2[4]);
+  const R A50 = R(-1.5) * dd, A51 = R(6) * xy, A52 = R(1.5) * uu;
+  const R A53 = S6 * bx, A54 = S6 * by, A55 = R(1) + R(1.5) * uu;
+  // Cholesky, columns in Gram-Schmidt order.
+  R* L = B.L;
+  const R r0 = rsqrt_t(A00);
+  L[0] = A10 * r0; L[1] = A20 * r0; L[3] = A30 * r0; L[6] = A40 * r0; L[10] = A50 * r0;
+  const R r1 = rsqrt_t(A11 - L[0] * L[0]);
+  L[2] = (A21 - L[1] * L[0]) * r1;
+  L[4] = (A31 - L[3] * L[0]) * r1;
+  L[7] = (A41 - L[6] * L[0]) * r1;
+  L[11] = (A51 - L[10] * L[0]) * r1;
+  const R r2 = rsqrt_t(A22 - L[1] * L[1] - L[2] * L[2]);
+  L[5] = (A32 - L[3] * L[1] - L[4] * L[2]) * r2;
+  L[8] = (A42 - L[6] * L[1] - L[7] * L[2]) * r2;
+  L[12] = (A52 - L[10] * L[1] - L[11] * L[2]) * r2;
+  const R r3 = rsqrt_t(A33 - L[3] * L[3] - L[4] * L[4] - L[5] * L[5]);
+  L[9] = (A43 - L[6] * L[3] - L[7] * L[4] - L[8] * L[5]) * r3;
+  L[13] = (A53 - L[10] * L[3] - L[11] * L[4] - L[12] * L[5]) * r3;
+  const R r4 = rsqrt_t(A44 - L[6] * L[6] - L[7] * L[7] - L[8] * L[8] - L[9] * L[9]);
+  L[14] = (A54 - L[10] * L[6] - L[11] * L[7] - L[12] * L[8] - L[13] * L[9]) * r4;
+  const R r5 = rsqrt_t(A55 - L[10] * L[10] - L[11] * L[11] - L[12] * L[12] - L[13] * L[13] -
+                       L[14] * L[14]);
+  B.r[0] = r0; B.r[1] = r1; B.r[2] = r2; B.r[3] = r3; B.r[4] = r4; B.r[5] = r5;
+}
+
+// Forward substitution x = L^-1 d.
+template <typename R>
+__device__ __forceinline__ void lower_solve(const Basis<R>& B, const R d[6], R x[6]) {
+  const R* L = B.L;
+  x[0] = d[0] * B.r[0];
+  x[1] = (d[1] - L[0] * x[0]) * B.r[1];
+  x[2] = (d[2] - L[1] * x[0] - L[2] * x[1]) * B.r[2];
+  x[3] = (d[3] - L[3] * x[0] - L[4] * x[1] - L[5] * x[2]) * B.r[3];
+  x[4] = (d[4] - L[6] * x[0] - L[7] * x[1] - L[8] * x[2] - L[9] * x[3]) * B.r[4];
+  x[5] = (d[5] - L[10] * x[0] - L[11] * x[1] - L[12] * x[2] - L[13] * x[3] - L[14] * x[4]) *
+         B.r[5];
+}
+
+// Back substitution y = L^-T v.
+template <typename R>
+__device__ __forceinline__ void upper_solve(const Basis<R>& B, const R v[6], R y[6]) {
+  const R* L = B.L;
+  y[5] = v[5] * B.r[5];
+  y[4] = (v[4] - L[14] * y[5]) * B.r[4];
+  y[3] = (v[3] - L[9] * y[4] - L[13] * y[5]) * B.r[3];
+  y[2] = (v[2] - L[5] * y[3] - L[8] * y[4] - L[12] * y[5]) * B.r[2];
+  y[1] = (v[1] - L[2] * y[2] - L[4] * y[3] - L[7] * y[4] - L[11] * y[5]) * B.r[1];
+  y[0] = (v[0] - L[0] * y[1] - L[1] * y[2] - L[3] * y[3] - L[6] * y[4] - L[10] * y[5]) *
+         B.r[0];
+}
+
+// One collision, eq. (6), on shifted populations h (in place).  Returns error
+// bits; on error h is left unchanged.
+template <typename R, int BASIS>
+__device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint64_t site,
+                                       uint64_t t) {
+  const Moments<R> m = hermite_moments(h);
+  const R rho = C.rho0 + m.drho;
+  if (!(rho > R(0)) || !(m.jx == m.jx) || !(m.jy == m.jy)) return kErrNonFinite;
+  const R inv = rcp_t(rho);
+  const R ux = m.jx * inv, uy = m.jy * inv;
+  // non-equilibrium Hermite moments d = M - M^0(rho,u), eq. (A5)
+  const R jxux = m.jx * ux, jyuy = m.jy * uy;
+  R d[6];
+  d[0] = m.M3 - R(1.5) * (jxux - jyuy);
+  d[1] = m.M4 - R(3) * m.jx * uy;
+  d[2] = m.M5 - R(1.5) * (jxux + jyuy);
+  d[3] = m.M6;
+  d[4] = m.M7;
+  d[5] = m.M8;
+
+  R N[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  R sr = R(0);
+  if (C.noise) {
+    site_gaussians<R>(C.k0, C.k1, site, t, 0u, N);
+    sr = sqrt(rho);
+  }
+
+  if (BASIS == kBasisHermite) {
+    // App. A: n = w m, relaxation of M - M^0 with the same amplitudes.
+    R Y[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) Y[a] = sr * C.xc[a] * N[a] - C.rt[a] * d[a];
+    R s[9];
+    hermite_back(Y, s);
+    constexpr R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+    h[0] += w0 * s[0];
+#pragma unroll
+    for (int i = 1; i < 5; ++i) h[i] += w1 * s[i];
+#pragma unroll
+    for (int i = 5; i < 9; ++i) h[i] += w5 * s[i];
+    return 0;
+  }
+
+  R bx = ux, by = uy;
+  if (BASIS == kBasisFnormLut) {
+    // nearest point of the 51 x 51 grid, spacing 0.02, [-0.5, 0.5]^2
+    const R fx = floor(ux / R(0.02) + R(0.5)), fy = floor(uy / R(0.02) + R(0.5));
+    if (!(fabs(fx) <= R(25) && fabs(fy) <= R(25))) return kErrInvalidVelocity;
+    bx = fx * R(0.02);
+    by = fy * R(0.02);
+  }
+  R g[9];
+  unit_equilibrium(bx, by, g);
+  R gmin = g[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) gmin = fmin(gmin, g[i]);
+  if (!(gmin > R(0))) return kErrInvalidVelocity;
+
+  Basis<R> B;
+  fnorm_basis(bx, by, B);
+  R Mt[6], D[6], y[6];
+  lower_solve(B, d, Mt);  // non-equilibrium f-norm moments M~^{3..8}
+#pragma unroll
+  for (int a = 0; a < 6; ++a) D[a] = sr * C.xc[a] * N[a] - C.rt[a] * Mt[a];
+  upper_solve(B, D, y);
+  // df_i = g_i [ sum_a m_i^a y_a - A - m~^1_i B1 - m~^2_i B2 ]
+  const R A = B.P0[0] * y[0] + B.P0[1] * y[1] + B.P0[2] * y[2];
+  const R B1 = B.P1[0] * y[0] + B.P1[1] * y[1] + B.P1[2] * y[2] + B.P1[3] * y[3] +
+               B.P1[4] * y[4];
+  const R B2 = B.P2[0] * y[0] + B.P2[1] * y[1] + B.P2[2] * y[2] + B.P2[3] * y[3] +
+               B.P2[4] * y[4];
+  constexpr R S3 = R(1.7320508075688772935);
+  const R Bx = S3 * B1, By = S3 * B2;
+  const R K = (Bx * bx + By * by) - A;
+  R s[9];
+  hermite_back(y, s);
+  h[0] += g[0] * (s[0] + K);
+  h[1] += g[1] * (s[1] + (K - Bx));
+  h[3] += g[3] * (s[3] + (K + Bx));
+  h[2] += g[2] * (s[2] + (K - By));
+  h[4] += g[4] * (s[4] + (K + By));
+  h[5] += g[5] * (s[5] + (K - (Bx + By)));
+  h[7] += g[7] * (s[7] + (K + (Bx + By)));
+  h[6] += g[6] * (s[6] + (K + (Bx - By)));
+  h[8] += g[8] * (s[8] + (K - (Bx - By)));
+  return 0;
+}
+
+}  // namespace flb

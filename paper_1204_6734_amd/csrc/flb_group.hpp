@@ -1,0 +1,92 @@
+// flb_group.hpp — a group of lattices ("slots") advanced by one batched step
+// launch per step on one stream (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+#include <vector>
+
+#include "flb.h"
+#include "flb_kernels.hpp"
+#include "flb_runtime.hpp"
+
+namespace flb {
+
+constexpr int kModeBlocks = 1024;
+
+struct Group {
+  std::vector<flb_params> P;
+  std::vector<SlotDesc> hdesc;
+  std::vector<int> prefix;
+  int storage = 1, compute = 1, basis = 0, total_tiles = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false, own_mem = false;
+  void* dev = nullptr;
+  size_t need_bytes = 0;
+  size_t max_lds = 65536;
+  // device arrays
+  SlotDesc* d_slots = nullptr;
+  int* d_prefix = nullptr;
+  uint64_t* d_clock = nullptr;
+  int* d_err = nullptr;
+  unsigned long long* d_err_step = nullptr;
+  double* d_open = nullptr;
+  double* d_B = nullptr;
+  double2* d_mode = nullptr;
+  double* d_io = nullptr;
+  int band_rows = 1;
+  std::vector<void*> pop;
+  std::vector<double*> d_partials, d_records;
+  double* d_skf = nullptr;
+  double2* d_z = nullptr;
+  double2* d_zt = nullptr;
+  double* d_skacc = nullptr;
+  double2* d_twx = nullptr;
+  double2* d_twy = nullptr;
+  // host state
+  uint64_t t = 0, nsk = 0;
+  int64_t err_step_host = -1;
+  std::vector<Stats> stats;
+  std::vector<std::vector<double>> mt0;
+  // graphs
+  int graph_chunk = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  // profiling
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  double prof_ms = 0;
+  uint64_t prof_launches = 0;
+
+  Group() = default;
+  Group(const Group&) = delete;
+  Group& operator=(const Group&) = delete;
+  ~Group();
+
+  void layout(Arena& a);
+  int init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t dev_bytes);
+  bool sample_due(int s, uint64_t tt) const;
+  bool sk_due(int s, uint64_t tt) const;
+  int after_step(uint64_t tt);
+  int launch_one(uint32_t k, bool sample);
+  bool graph_friendly() const;
+  uint64_t steps_to_close() const;
+  int capture_graph();
+  int step(uint64_t nsteps);
+  int sync();
+  int read_populations(int s, double* f);
+  int set_populations(int s, const double* f, uint64_t tnew);
+  int set_fields(int s, const double* rho, const double* ux, const double* uy);
+  int read_moments(int s, int at, double* m);
+  int read_covariance(int s, flb_cov* out);
+  int reset_stats();
+  int read_structure_factor(int which, double* out);
+  int read_fourier_mode(int which, int kx, int ky, double out[2]);
+  size_t checkpoint_bytes() const;
+  int checkpoint(void* host, size_t bytes);
+  int restore(const void* host, size_t bytes);
+  int kernel_time(double* ms, uint64_t* launches);
+};
+
+}  // namespace flb

@@ -1,0 +1,722 @@
+// flb_kernels.hip — HIP kernels of libflb for gfx950 (MI355X).
+//
+// The hot kernel is step_kernel: one fused fluctuating collide-and-stream
+// update (Kaehler & Wagner, Sec. II eq. (6) with the f-norm basis of
+// Sec. IV) over every site of one or more lattices ("slots"), with the
+// correlator sums of eqs. (16)/(23) and the structure-factor fields of
+// eqs. (24)-(26) fused in when a sample is due.
+//
+// Memory layout: one population array per lattice, structure of arrays
+// [9][ny][nx] of shifted values h_i = f_i - w_i rho0 (FP32 or FP64), updated
+// in place with the two-phase "AA" access pattern: on even steps a site
+// reads its own nine slots and writes the post-collision values back
+// reversed; on odd steps it reads the reversed values of its neighbours and
+// writes forward to its neighbours.  Each site touches the same nine
+// locations it reads, so no second buffer is needed.  One 256-thread block
+// updates a 64 x 4 tile: every wavefront reads and writes whole rows.
+// Blocks are renumbered so that each XCD (blocks are dealt to the eight
+// XCDs round-robin) sweeps a contiguous band of rows and keeps its halo
+// rows in its own L2.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "flb_device.hpp"
+#include "flb_kernels.hpp"
+
+namespace flb {
+
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
+  return xcd * q + (xcd < r ? xcd : r) + (bid >> 3);
+}
+
+__device__ __forceinline__ int find_slot(const int* __restrict__ prefix, int nslots, int tile) {
+  int lo = 0, hi = nslots;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= tile) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Element indices of the nine populations a site reads in phase `odd`.
+// After the collision the value of direction kOpp[i] goes back to idx[i].
+__device__ __forceinline__ void site_indices(int x, int y, int nx, int ny, int odd,
+                                             uint32_t N, uint32_t idx[9]) {
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const uint32_t rc = (uint32_t)y * nx, rm = (uint32_t)ym * nx, rp = (uint32_t)yp * nx;
+  const uint32_t c = rc + x;
+  if (!odd) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) idx[i] = (uint32_t)i * N + c;
+  } else {
+    // plane opp(i) at x - v_i
+    idx[0] = c;
+    idx[1] = 3u * N + rc + xm;   // v=( 1, 0): plane 3 at (x-1, y)
+    idx[2] = 4u * N + rm + x;    // v=( 0, 1): plane 4 at (x, y-1)
+    idx[3] = 1u * N + rc + xp;   // v=(-1, 0): plane 1 at (x+1, y)
+    idx[4] = 2u * N + rp + x;    // v=( 0,-1): plane 2 at (x, y+1)
+    idx[5] = 7u * N + rm + xm;   // v=( 1, 1): plane 7 at (x-1, y-1)
+    idx[6] = 8u * N + rm + xp;   // v=(-1, 1): plane 8 at (x+1, y-1)
+    idx[7] = 5u * N + rp + xp;   // v=(-1,-1): plane 5 at (x+1, y+1)
+    idx[8] = 6u * N + rp + xm;   // v=( 1,-1): plane 6 at (x-1, y+1)
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ CollideConst<R> collide_const(const SlotDesc& sd);
+
+template <>
+__device__ __forceinline__ CollideConst<float> collide_const<float>(const SlotDesc& sd) {
+  CollideConst<float> C;
+  C.rho0 = sd.rho0f;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    C.rt[a] = sd.rtf[a];
+    C.xc[a] = sd.xcf[a];
+  }
+  C.k0 = sd.k0;
+  C.k1 = sd.k1;
+  C.noise = sd.noise;
+  return C;
+}
+
+template <>
+__device__ __forceinline__ CollideConst<double> collide_const<double>(const SlotDesc& sd) {
+  CollideConst<double> C;
+  C.rho0 = sd.rho0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    C.rt[a] = sd.rt[a];
+    C.xc[a] = sd.xc[a];
+  }
+  C.k0 = sd.k0;
+  C.k1 = sd.k1;
+  C.noise = sd.noise;
+  return C;
+}
+
+// Sum of 54 per-lane values over a 64-lane wavefront, transposed: after six
+// butterfly passes that each halve the number of values a lane carries,
+// lane l holds the wave total of value l (values 54..63 are zero).
+__device__ __forceinline__ double wave_transpose_sum(double (&v)[64], int lane) {
+#pragma unroll
+  for (int off = 32, n = 32; off >= 1; off >>= 1, n >>= 1) {
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const double send = up ? v[k] : v[k + n];
+      const double keep = up ? v[k + n] : v[k];
+      v[k] = keep + __shfl_xor(send, off, 64);
+    }
+  }
+  return v[0];
+}
+
+// Correlator sums of df_i = f_i - f_i^0(rho0, u0): 9 first moments and the
+// 45 products i <= j, added to this tile's open time-block partials.
+template <typename R>
+__device__ __forceinline__ void sample_correlators(const R h[9], bool active,
+                                                   const SlotDesc& sd, int tile_local) {
+  __shared__ double red[kTileY][kTileX];
+  double v[64];
+  double df[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) df[i] = active ? (double)h[i] - sd.e[i] : 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = df[i];
+  int k = 9;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = i; j < 9; ++j) v[k++] = df[i] * df[j];
+#pragma unroll
+  for (int q = 54; q < 64; ++q) v[q] = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double s = wave_transpose_sum(v, lane);
+  red[wave][lane] = s;
+  __syncthreads();
+  if (threadIdx.x < kNStat) {
+    const double tot = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                       (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    double* p = sd.partials + (size_t)tile_local * kNStat + threadIdx.x;
+    *p += tot;
+  }
+}
+
+template <typename S, typename R, int BASIS, bool SAMPLE>
+__global__ __launch_bounds__(kBlock) void step_kernel(const SlotDesc* __restrict__ slots,
+                                                      const int* __restrict__ prefix,
+                                                      int nslots,
+                                                      const uint64_t* __restrict__ clock,
+                                                      uint32_t step_idx) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = find_slot(prefix, nslots, tile);
+  const SlotDesc& sd = slots[s];
+  const uint64_t t = sd.t0 + *clock + step_idx;
+  if (t >= sd.tend) return;
+  const int lt = tile - prefix[s];
+  const int nx = sd.nx, ny = sd.ny;
+  const int ty = lt / sd.tiles_x, tx = lt - ty * sd.tiles_x;
+  const int x = tx * kTileX + (threadIdx.x & (kTileX - 1));
+  const int y = ty * kTileY + (threadIdx.x >> 6);
+  const bool active = (x < nx) && (y < ny);
+  const uint32_t N = (uint32_t)nx * (uint32_t)ny;
+  S* __restrict__ pop = (S*)sd.pop;
+
+  uint32_t idx[9];
+  R h[9];
+  if (active) {
+    site_indices(x, y, nx, ny, (int)(t & 1), N, idx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = (R)pop[idx[i]];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = R(0);
+  }
+
+  if (SAMPLE) {
+    if (sd.sample_every > 0 && t % (uint64_t)sd.sample_every == 0)
+      sample_correlators<R>(h, active, sd, lt);
+    if (sd.skf != nullptr && sd.sk_every > 0 && t % (uint64_t)sd.sk_every == 0 && active) {
+      // structure-factor fields in the f-norm at (rho0, u0): d rho,
+      // dj~_x = sqrt3 (j_x - u_x0 rho), dj~_y = sqrt3 (j_y - u_y0 rho)  (eq. (34))
+      double hd[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) hd[i] = (double)h[i];
+      const Moments<double> m = hermite_moments(hd);
+      const double rho = sd.rho0 + m.drho;
+      const uint32_t site = (uint32_t)y * nx + x;
+      sd.skf[site] = m.drho;
+      sd.skf[N + site] = 1.7320508075688772935 * (m.jx - sd.ux0 * rho);
+      sd.skf[2u * N + site] = 1.7320508075688772935 * (m.jy - sd.uy0 * rho);
+    }
+  }
+
+  if (!active) return;
+  const CollideConst<R> C = collide_const<R>(sd);
+  const uint64_t site = (uint64_t)y * (uint64_t)nx + (uint64_t)x;
+  const int e = collide<R, BASIS>(h, C, site, t);
+  if (e) {
+    atomicOr(sd.err, e);
+    atomicMin(sd.err_step, (unsigned long long)t);
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) pop[idx[i]] = (S)h[kOpp[i]];
+}
+
+__global__ void tick_kernel(uint64_t* clock, uint64_t n) { *clock += n; }
+
+// ---------------------------------------------------------------- state I/O
+// Write f (unshifted FP64, natural order, [9][ny][nx]) into storage at phase
+// `odd` (odd: the reversed, un-streamed layout the next odd step reads).
+template <typename S>
+__global__ void write_state_kernel(S* pop, const double* __restrict__ f, int nx, int ny,
+                                   int odd, double rho0, int y0, int rows) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
+  if (x >= nx) return;
+  const uint32_t B = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
+  constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
+  uint32_t idx[9];
+  site_indices(x, y, nx, ny, odd, N, idx);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) pop[idx[i]] = (S)(f[i * (size_t)B + bs] - w[i] * rho0);
+  (void)site;
+}
+
+template <typename S>
+__global__ void read_state_kernel(const S* __restrict__ pop, double* f, int nx, int ny, int odd,
+                                  double rho0, int y0, int rows) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
+  if (x >= nx) return;
+  const uint32_t B = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
+  constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
+  uint32_t idx[9];
+  site_indices(x, y, nx, ny, odd, N, idx);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i * (size_t)B + bs] = (double)pop[idx[i]] + w[i] * rho0;
+  (void)site;
+}
+
+// Raw storage copy in natural (even-phase) order for checkpoints: keeps the
+// stored bits exactly.
+template <typename S>
+__global__ void raw_state_kernel(S* pop, S* buf, int nx, int ny, int odd, int to_buf, int y0,
+                                 int rows) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
+  if (x >= nx) return;
+  const uint32_t B = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
+  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
+  uint32_t idx[9];
+  site_indices(x, y, nx, ny, odd, N, idx);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if (to_buf) buf[i * (size_t)B + bs] = pop[idx[i]];
+    else pop[idx[i]] = buf[i * (size_t)B + bs];
+  }
+  (void)site;
+}
+
+// Equilibrium f^0(rho(x), u(x)) from per-site fields (or uniform values when
+// the field pointers are null), optionally plus ideal-gas fluctuations
+// sqrt(mu f^0_i) N_i drawn with the thermal tag (two draws per site:
+// step field 0 gives N_0..N_5, step field 1 gives N_6..N_8).
+template <typename S>
+__global__ void init_kernel(S* pop, const double* __restrict__ rho, const double* __restrict__ ux,
+                            const double* __restrict__ uy, double rho0, double ux0, double uy0,
+                            int nx, int ny, double mu, uint32_t k0, uint32_t k1, int odd,
+                            int y0, int rows) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
+  if (x >= nx) return;
+  const uint32_t bs = (uint32_t)blockIdx.y * nx + x;  // index into band fields
+  (void)rows;
+  constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
+  const double r = rho ? rho[bs] : rho0;
+  const double vx = ux ? ux[bs] : ux0, vy = uy ? uy[bs] : uy0;
+  double g[9];
+  unit_equilibrium(vx, vy, g);
+  double n9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (mu > 0.0) {
+    double a[6], b[6];
+    site_gaussians<double>(k0, k1, site, 0, 0x80000000u, a);
+    site_gaussians<double>(k0, k1, site, 1, 0x80000000u, b);
+    for (int i = 0; i < 6; ++i) n9[i] = a[i];
+    for (int i = 0; i < 3; ++i) n9[6 + i] = b[i];
+  }
+  uint32_t idx[9];
+  site_indices(x, y, nx, ny, odd, N, idx);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double f0 = r * g[i];
+    const double f = mu > 0.0 ? f0 + sqrt(mu * f0) * n9[i] : f0;
+    pop[idx[i]] = (S)(f - w[i] * rho0);
+  }
+}
+
+// Moments B f per site (B row-major 9x9 in global memory), or the local
+// f-norm moments when B is null: M~^0 = rho, M~^1 = M~^2 = 0 (local
+// velocity), M~^{3..8} = L^-1 d.
+template <typename S>
+__global__ void moments_kernel(const S* __restrict__ pop, const double* __restrict__ B,
+                               double* out, int nx, int ny, int odd, double rho0, int* err,
+                               int y0, int rows) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
+  if (x >= nx) return;
+  const uint32_t Bn = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
+  constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
+  uint32_t idx[9];
+  site_indices(x, y, nx, ny, odd, N, idx);
+  double h[9], f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    h[i] = (double)pop[idx[i]];
+    f[i] = h[i] + w[i] * rho0;
+  }
+  if (B) {
+    for (int a = 0; a < 9; ++a) {
+      double sacc = 0.0;
+      for (int i = 0; i < 9; ++i) sacc += B[a * 9 + i] * f[i];
+      out[a * (size_t)Bn + bs] = sacc;
+    }
+    return;
+  }
+  const Moments<double> m = hermite_moments(h);
+  const double rho = rho0 + m.drho, ux = m.jx / rho, uy = m.jy / rho;
+  double g[9];
+  unit_equilibrium(ux, uy, g);
+  double gmin = g[0];
+  for (int i = 1; i < 9; ++i) gmin = fmin(gmin, g[i]);
+  if (!(gmin > 0.0)) atomicOr(err, kErrInvalidVelocity);
+  Basis<double> Bs;
+  fnorm_basis(ux, uy, Bs);
+  const double jxux = m.jx * ux, jyuy = m.jy * uy;
+  double d[6] = {m.M3 - 1.5 * (jxux - jyuy), m.M4 - 3.0 * m.jx * uy,
+                 m.M5 - 1.5 * (jxux + jyuy), m.M6, m.M7, m.M8};
+  double Mt[6];
+  lower_solve(Bs, d, Mt);
+  out[bs] = rho;
+  out[Bn + bs] = 0.0;
+  out[2 * (size_t)Bn + bs] = 0.0;
+  for (int a = 0; a < 6; ++a) out[(3 + a) * (size_t)Bn + bs] = Mt[a];
+  (void)site;
+}
+
+// Partial sums of one Fourier coefficient sum_x dA(x) e^{-i k.x} per block.
+template <typename S>
+__global__ void fourier_mode_kernel(const S* __restrict__ pop, double2* partial, int nx, int ny,
+                                    int odd, int which, int kx, int ky, double rho0, double ux0,
+                                    double uy0) {
+  __shared__ double sr[256], si[256];
+  const int tid = threadIdx.x;
+  const uint32_t N = (uint32_t)nx * ny;
+  double ar = 0.0, ai = 0.0;
+  for (uint32_t site = blockIdx.x * 256u + tid; site < N; site += gridDim.x * 256u) {
+    const int y = (int)(site / (uint32_t)nx), x = (int)(site - (uint32_t)y * nx);
+    uint32_t idx[9];
+    site_indices(x, y, nx, ny, odd, N, idx);
+    double h[9];
+    for (int i = 0; i < 9; ++i) h[i] = (double)pop[idx[i]];
+    const Moments<double> m = hermite_moments(h);
+    const double rho = rho0 + m.drho;
+    double a = m.drho;
+    if (which == 1) a = 1.7320508075688772935 * (m.jx - ux0 * rho);
+    if (which == 2) a = 1.7320508075688772935 * (m.jy - uy0 * rho);
+    const long long px = ((long long)kx * x) % nx, py = ((long long)ky * y) % ny;
+    const double ph = 2.0 * ((double)px / nx + (double)py / ny);
+    double sn, cs;
+    sincospi(ph, &sn, &cs);
+    ar += a * cs;
+    ai -= a * sn;
+  }
+  sr[tid] = ar;
+  si[tid] = ai;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      sr[tid] += sr[tid + o];
+      si[tid] += si[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) partial[blockIdx.x] = make_double2(sr[0], si[0]);
+}
+
+// ------------------------------------------------------------ time blocks
+// Close the open time block of a lattice: record[slot] = sum over tiles of
+// the partials (fixed order), then clear the partials.
+__global__ void close_block_kernel(double* partials, int ntiles, double* record) {
+  const int v = threadIdx.x;
+  if (v >= kNStat) return;
+  double s = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    s += partials[(size_t)t * kNStat + v];
+    partials[(size_t)t * kNStat + v] = 0.0;
+  }
+  record[v] = s;
+}
+
+// Neighbouring records merge pairwise: rec[b] = rec[2b] + rec[2b+1].
+__global__ void merge_blocks_kernel(double* rec, int nhalf) {
+  const int v = threadIdx.x;
+  if (v >= kNStat) return;
+  for (int b = 0; b < nhalf; ++b)
+    rec[(size_t)b * kNStat + v] = rec[(size_t)(2 * b) * kNStat + v] +
+                                  rec[(size_t)(2 * b + 1) * kNStat + v];
+}
+
+// Sum of the open partials (fixed order) into out[kNStat].
+__global__ void open_sum_kernel(const double* partials, int ntiles, double* out) {
+  const int v = threadIdx.x;
+  if (v >= kNStat) return;
+  double s = 0.0;
+  for (int t = 0; t < ntiles; ++t) s += partials[(size_t)t * kNStat + v];
+  out[v] = s;
+}
+
+__global__ void fill_kernel(double* p, size_t n, double value) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+// -------------------------------------------------------- structure factor
+// Complex rows: z1 = d rho + i dj~_x, z2 = dj~_y (+ 0 i).
+__global__ void sk_pack_kernel(const double* __restrict__ f, double2* z, uint32_t N) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  z[i] = make_double2(f[i], f[N + i]);
+  z[N + i] = make_double2(f[2u * N + i], 0.0);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-LDS radix-2 decimation-in-time FFT of one row of length n (power of
+// two) per block: bit-reversed load, log2 n butterfly stages.  tw[k] =
+// exp(-2 pi i k / n), k < n/2.
+__global__ void fft_rows_pow2_kernel(const double2* __restrict__ in, double2* out, int n,
+                                     int logn, const double2* __restrict__ tw) {
+  extern __shared__ double2 buf[];
+  const size_t row = blockIdx.x;
+  const double2* src = in + row * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = (int)(__brev((unsigned)i) >> (32 - logn));
+    buf[r] = src[i];
+  }
+  __syncthreads();
+  for (int s = 1; s <= logn; ++s) {
+    const int half = 1 << (s - 1);
+    const int stride = n >> s;  // twiddle step
+    for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
+      const int grp = b / half, j = b - grp * half;
+      const int i0 = grp * 2 * half + j, i1 = i0 + half;
+      const double2 wv = tw[j * stride];
+      const double2 u = buf[i0], v = cmul(wv, buf[i1]);
+      buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+      buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+  double2* dst = out + row * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = buf[i];
+}
+
+// Direct DFT of rows of any length n: out[k] = sum_j in[j] tw[(j k) mod n],
+// tw[m] = exp(-2 pi i m / n), m < n.
+__global__ void dft_rows_kernel(const double2* __restrict__ in, double2* out, int n,
+                                const double2* __restrict__ tw) {
+  const size_t row = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double2* src = in + row * n;
+  double sr = 0.0, si = 0.0;
+  int m = 0;
+  for (int j = 0; j < n; ++j) {
+    const double2 a = src[j], wv = tw[m];
+    sr += a.x * wv.x - a.y * wv.y;
+    si += a.x * wv.y + a.y * wv.x;
+    m += k;
+    if (m >= n) m -= n;
+  }
+  out[row * n + k] = make_double2(sr, si);
+}
+
+// out[c][r] = in[r][c] for a rows x cols complex matrix (32 x 32 LDS tiles).
+__global__ void transpose_kernel(const double2* __restrict__ in, double2* out, int rows,
+                                 int cols) {
+  __shared__ double2 tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const size_t z = blockIdx.z;
+  const double2* src = in + z * (size_t)rows * cols;
+  double2* dst = out + z * (size_t)rows * cols;
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int r = by + j, c = bx + threadIdx.x;
+    if (r < rows && c < cols) tile[j][threadIdx.x] = src[(size_t)r * cols + c];
+  }
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int c = bx + j, r = by + threadIdx.x;
+    if (r < rows && c < cols) dst[(size_t)c * rows + r] = tile[threadIdx.x][j];
+  }
+}
+
+// Accumulate |d rho(k)|^2, |dj~_x(k)|^2, |dj~_y(k)|^2 and dj~_x(k) dj~_y(-k)
+// from the transformed packed fields (stored transposed: [kx][ky]).  With
+// z1 = a + i b for real a, b: a(k) = (Z1(k) + conj Z1(-k))/2,
+// b(k) = (Z1(k) - conj Z1(-k))/(2i).
+__global__ void sk_accumulate_kernel(const double2* __restrict__ Zt, double* acc, int nx,
+                                     int ny) {
+  const uint32_t N = (uint32_t)nx * ny;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int kx = (int)(i / (uint32_t)ny), ky = (int)(i - (uint32_t)kx * ny);
+  const int mkx = kx == 0 ? 0 : nx - kx, mky = ky == 0 ? 0 : ny - ky;
+  const double2 z = Zt[i], zm = Zt[(uint32_t)mkx * ny + mky];
+  const double2 c = Zt[N + i];
+  const double ar = 0.5 * (z.x + zm.x), ai = 0.5 * (z.y - zm.y);
+  const double br = 0.5 * (z.y + zm.y), bi = -0.5 * (z.x - zm.x);
+  const uint32_t o = (uint32_t)ky * nx + kx;
+  acc[o] += ar * ar + ai * ai;
+  acc[N + o] += br * br + bi * bi;
+  acc[2u * N + o] += c.x * c.x + c.y * c.y;
+  acc[3u * N + o] += br * c.x + bi * c.y;   // Re(b conj c)
+  acc[4u * N + o] += bi * c.x - br * c.y;   // Im(b conj c)
+}
+
+// ------------------------------------------------------------ launchers
+template <typename S, typename R, int BASIS>
+static hipError_t launch_step_t(bool sample, const SlotDesc* d_slots, const int* d_prefix,
+                                int nslots, int total_tiles, const uint64_t* d_clock,
+                                uint32_t step_idx, hipStream_t st) {
+  if (total_tiles <= 0) return hipSuccess;
+  if (sample)
+    hipLaunchKernelGGL((step_kernel<S, R, BASIS, true>), dim3(total_tiles), dim3(kBlock), 0, st,
+                       d_slots, d_prefix, nslots, d_clock, step_idx);
+  else
+    hipLaunchKernelGGL((step_kernel<S, R, BASIS, false>), dim3(total_tiles), dim3(kBlock), 0,
+                       st, d_slots, d_prefix, nslots, d_clock, step_idx);
+  return hipGetLastError();
+}
+
+template <typename S, typename R>
+static hipError_t launch_step_b(int basis, bool sample, const SlotDesc* a, const int* b, int c,
+                                int d, const uint64_t* e, uint32_t f, hipStream_t g) {
+  switch (basis) {
+    case kBasisFnormLocal: return launch_step_t<S, R, kBasisFnormLocal>(sample, a, b, c, d, e, f, g);
+    case kBasisHermite: return launch_step_t<S, R, kBasisHermite>(sample, a, b, c, d, e, f, g);
+    case kBasisFnormLut: return launch_step_t<S, R, kBasisFnormLut>(sample, a, b, c, d, e, f, g);
+  }
+  return hipErrorInvalidValue;
+}
+
+// storage: 0 = FP64, 1 = FP32 shifted; compute: 0 = FP64, 1 = FP32.
+hipError_t launch_step(int storage, int compute, int basis, bool sample, const SlotDesc* d_slots,
+                       const int* d_prefix, int nslots, int total_tiles,
+                       const uint64_t* d_clock, uint32_t step_idx, hipStream_t st) {
+  if (storage == 0)
+    return launch_step_b<double, double>(basis, sample, d_slots, d_prefix, nslots, total_tiles,
+                                         d_clock, step_idx, st);
+  if (compute == 0)
+    return launch_step_b<float, double>(basis, sample, d_slots, d_prefix, nslots, total_tiles,
+                                        d_clock, step_idx, st);
+  return launch_step_b<float, float>(basis, sample, d_slots, d_prefix, nslots, total_tiles,
+                                     d_clock, step_idx, st);
+}
+
+hipError_t launch_tick(uint64_t* d_clock, uint64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, d_clock, n);
+  return hipGetLastError();
+}
+
+static dim3 row_grid(int nx, int rows) { return dim3((nx + 255) / 256, rows); }
+
+// The row-parallel utility kernels below process the band of rows
+// [y0, y0 + rows); their host-side arrays hold that band only.
+hipError_t launch_write_state(int storage, void* pop, const double* f, int nx, int ny, int odd,
+                              double rho0, int y0, int rows, hipStream_t st) {
+  if (storage == 0)
+    hipLaunchKernelGGL(write_state_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
+                       (double*)pop, f, nx, ny, odd, rho0, y0, rows);
+  else
+    hipLaunchKernelGGL(write_state_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
+                       (float*)pop, f, nx, ny, odd, rho0, y0, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_state(int storage, const void* pop, double* f, int nx, int ny, int odd,
+                             double rho0, int y0, int rows, hipStream_t st) {
+  if (storage == 0)
+    hipLaunchKernelGGL(read_state_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
+                       (const double*)pop, f, nx, ny, odd, rho0, y0, rows);
+  else
+    hipLaunchKernelGGL(read_state_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
+                       (const float*)pop, f, nx, ny, odd, rho0, y0, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_raw_state(int storage, void* pop, void* buf, int nx, int ny, int odd,
+                            int to_buf, int y0, int rows, hipStream_t st) {
+  if (storage == 0)
+    hipLaunchKernelGGL(raw_state_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
+                       (double*)pop, (double*)buf, nx, ny, odd, to_buf, y0, rows);
+  else
+    hipLaunchKernelGGL(raw_state_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
+                       (float*)pop, (float*)buf, nx, ny, odd, to_buf, y0, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, void* pop, const double* rho, const double* ux,
+                       const double* uy, double rho0, double ux0, double uy0, int nx, int ny,
+                       double mu, uint32_t k0, uint32_t k1, int odd, int y0, int rows,
+                       hipStream_t st) {
+  if (storage == 0)
+    hipLaunchKernelGGL(init_kernel<double>, row_grid(nx, rows), dim3(256), 0, st, (double*)pop,
+                       rho, ux, uy, rho0, ux0, uy0, nx, ny, mu, k0, k1, odd, y0, rows);
+  else
+    hipLaunchKernelGGL(init_kernel<float>, row_grid(nx, rows), dim3(256), 0, st, (float*)pop,
+                       rho, ux, uy, rho0, ux0, uy0, nx, ny, mu, k0, k1, odd, y0, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, const void* pop, const double* B, double* out, int nx,
+                          int ny, int odd, double rho0, int* err, int y0, int rows,
+                          hipStream_t st) {
+  if (storage == 0)
+    hipLaunchKernelGGL(moments_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
+                       (const double*)pop, B, out, nx, ny, odd, rho0, err, y0, rows);
+  else
+    hipLaunchKernelGGL(moments_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
+                       (const float*)pop, B, out, nx, ny, odd, rho0, err, y0, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_fourier_mode(int storage, const void* pop, double2* partial, int nblocks,
+                               int nx, int ny, int odd, int which, int kx, int ky, double rho0,
+                               double ux0, double uy0, hipStream_t st) {
+  if (storage == 0)
+    hipLaunchKernelGGL(fourier_mode_kernel<double>, dim3(nblocks), dim3(256), 0, st,
+                       (const double*)pop, partial, nx, ny, odd, which, kx, ky, rho0, ux0, uy0);
+  else
+    hipLaunchKernelGGL(fourier_mode_kernel<float>, dim3(nblocks), dim3(256), 0, st,
+                       (const float*)pop, partial, nx, ny, odd, which, kx, ky, rho0, ux0, uy0);
+  return hipGetLastError();
+}
+
+hipError_t launch_close_block(double* partials, int ntiles, double* record, hipStream_t st) {
+  hipLaunchKernelGGL(close_block_kernel, dim3(1), dim3(64), 0, st, partials, ntiles, record);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_blocks(double* rec, int nhalf, hipStream_t st) {
+  hipLaunchKernelGGL(merge_blocks_kernel, dim3(1), dim3(64), 0, st, rec, nhalf);
+  return hipGetLastError();
+}
+
+hipError_t launch_open_sum(const double* partials, int ntiles, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(open_sum_kernel, dim3(1), dim3(64), 0, st, partials, ntiles, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+static int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+// Row transforms of `rows` rows of length n; tw holds n/2 entries for powers
+// of two (LDS path) and n entries otherwise (direct DFT).
+static hipError_t row_transform(const double2* in, double2* out, int n, int rows,
+                                const double2* tw, size_t max_lds, hipStream_t st) {
+  if (is_pow2(n) && (size_t)n * sizeof(double2) <= max_lds) {
+    const int threads = n / 2 < 1024 ? (n / 2 < 64 ? 64 : n / 2) : 1024;
+    const size_t lds = (size_t)n * sizeof(double2);
+    hipLaunchKernelGGL(fft_rows_pow2_kernel, dim3(rows), dim3(threads), lds, st, in, out, n,
+                       ilog2(n), tw);
+  } else {
+    hipLaunchKernelGGL(dft_rows_kernel, dim3((n + 127) / 128, rows), dim3(128), 0, st, in, out,
+                       n, tw);
+  }
+  return hipGetLastError();
+}
+
+hipError_t sk_prepare(size_t max_lds) {
+  return hipFuncSetAttribute((const void*)fft_rows_pow2_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+}
+
+// Full structure-factor sample: fields (already written by the step kernel)
+// -> packed complex rows -> x transforms -> transpose -> y transforms ->
+// accumulate.  z, zt: 2 N complex scratch each.
+hipError_t launch_sk_sample(const double* fields, double2* z, double2* zt, double* acc, int nx,
+                            int ny, const double2* twx, const double2* twy, size_t max_lds,
+                            hipStream_t st) {
+  const uint32_t N = (uint32_t)nx * ny;
+  hipLaunchKernelGGL(sk_pack_kernel, dim3((N + 255) / 256), dim3(256), 0, st, fields, z, N);
+  hipError_t e = row_transform(z, zt, nx, 2 * ny, twx, max_lds, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(transpose_kernel, dim3((nx + 31) / 32, (ny + 31) / 32, 2), dim3(32, 8), 0,
+                     st, zt, z, ny, nx);
+  e = row_transform(z, zt, ny, 2 * nx, twy, max_lds, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sk_accumulate_kernel, dim3((N + 255) / 256), dim3(256), 0, st, zt, acc, nx,
+                     ny);
+  return hipGetLastError();
+}
+
+}  // namespace flb

@@ -1,0 +1,39 @@
+// flb_kernels.hpp — device-side data structures shared by the kernels and
+// the host runtime of libflb (internal; not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flb {
+
+constexpr int kTileX = 64;   // one wavefront per tile row: coalesced rows
+constexpr int kTileY = 4;    // four wavefronts per 256-thread block
+constexpr int kBlock = kTileX * kTileY;
+constexpr int kNStat = 54;   // 9 first moments + 45 unique second moments
+constexpr int kMaxTimeBlocks = 1024;
+enum : int { kErrInvalidVelocity = 1, kErrNonFinite = 2 };
+
+// One lattice ("slot") as seen by the batched step kernel.  All slots of a
+// launch share the storage and compute types and the basis variant.
+struct SlotDesc {
+  void* pop;            // storage [9][ny][nx], shifted h = f - w rho0
+  double* partials;     // [ntiles][kNStat] open time-block sums (sampling)
+  double* skf;          // [3][ny][nx] structure-factor fields or null
+  int* err;             // error bits (atomicOr)
+  unsigned long long* err_step;  // first failing step (atomicMin)
+  int nx, ny, tiles_x, ntiles;
+  uint64_t t0;          // own time = t0 + clock (mod 2^64)
+  uint64_t tend;        // no update once own time >= tend
+  uint32_t k0, k1;      // Philox key = seed
+  int sample_every;     // 0: never
+  int sk_every;         // 0: never
+  int noise;
+  int pad_;
+  double rho0, ux0, uy0;
+  double rt[6], xc[6];  // 1/tau, noise coefficients
+  double e[9];          // f_i^0(rho0,u0) - w_i rho0 (sampling reference)
+  float rho0f, rtf[6], xcf[6], padf_;  // single-precision copies
+};
+
+}  // namespace flb

@@ -1,0 +1,287 @@
+// flb_runtime.cpp — host runtime behind the C ABI of include/flb.h:
+// lattices (one slot) and ensembles (many slots of one shape), device
+// memory arenas, time-block statistics, structure-factor pipeline,
+// checkpoints and the measurement basis at (rho0, u0).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "flb.h"
+#include "flb_kernels.hpp"
+#include "flb_runtime.hpp"
+
+namespace flb {
+
+// ----------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return set_error(FLB_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPC(expr)                                   \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+// ------------------------------------------------------------ host math
+// Hermite rows of eq. (A3) and the D2Q9 weights of eq. (A2).
+static const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const int kVXh[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int kVYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+void hermite_rows(double m[81]) {
+  // rows as functions of the velocity: 1, sqrt3 vx, sqrt3 vy,
+  // (3vx^2-3vy^2)/2, 3 vx vy, (3vx^2+3vy^2)/2 - 1, sqrt(3/2) vx (3vy^2-1),
+  // sqrt(3/2) vy (3vx^2-1), (3vx^2-1)(3vy^2-1)/2
+  for (int i = 0; i < 9; ++i) {
+    const double x = kVXh[i], y = kVYh[i];
+    const double hx = 3 * x * x - 1, hy = 3 * y * y - 1;
+    m[0 * 9 + i] = 1;
+    m[1 * 9 + i] = std::sqrt(3.0) * x;
+    m[2 * 9 + i] = std::sqrt(3.0) * y;
+    m[3 * 9 + i] = 1.5 * (x * x - y * y);
+    m[4 * 9 + i] = 3 * x * y;
+    m[5 * 9 + i] = 1.5 * (x * x + y * y) - 1;
+    m[6 * 9 + i] = std::sqrt(1.5) * x * hy;
+    m[7 * 9 + i] = std::sqrt(1.5) * y * hx;
+    m[8 * 9 + i] = 0.5 * hx * hy;
+  }
+}
+
+double equilibrium(int i, double rho, double ux, double uy) {
+  const double c = ux * kVXh[i] + uy * kVYh[i];
+  return rho * kW[i] * (1 + 3 * c + 4.5 * c * c - 1.5 * (ux * ux + uy * uy));
+}
+
+// f-norm rows at velocity u: m~ = L^-1 m with L L^T = m diag(g) m^T (the
+// Gram-Schmidt of Sec. IV written as a Cholesky factorisation).  Returns
+// false outside the validity region.
+bool fnorm_rows(double ux, double uy, double mt[81]) {
+  double m[81], g[9], G[81], L[81];
+  hermite_rows(m);
+  for (int i = 0; i < 9; ++i) {
+    g[i] = equilibrium(i, 1.0, ux, uy);
+    if (!(g[i] > 0)) return false;
+  }
+  for (int a = 0; a < 9; ++a)
+    for (int b = 0; b < 9; ++b) {
+      double s = 0;
+      for (int i = 0; i < 9; ++i) s += m[a * 9 + i] * g[i] * m[b * 9 + i];
+      G[a * 9 + b] = s;
+    }
+  std::memset(L, 0, sizeof(L));
+  for (int j = 0; j < 9; ++j) {
+    double d = G[j * 9 + j];
+    for (int k = 0; k < j; ++k) d -= L[j * 9 + k] * L[j * 9 + k];
+    if (!(d > 0)) return false;
+    L[j * 9 + j] = std::sqrt(d);
+    for (int i = j + 1; i < 9; ++i) {
+      double s = G[i * 9 + j];
+      for (int k = 0; k < j; ++k) s -= L[i * 9 + k] * L[j * 9 + k];
+      L[i * 9 + j] = s / L[j * 9 + j];
+    }
+  }
+  for (int c = 0; c < 9; ++c)
+    for (int a = 0; a < 9; ++a) {
+      double s = m[a * 9 + c];
+      for (int k = 0; k < a; ++k) s -= L[a * 9 + k] * mt[k * 9 + c];
+      mt[a * 9 + c] = s / L[a * 9 + a];
+    }
+  return true;
+}
+
+static bool valid_velocity(double ux, double uy) {
+  for (int i = 0; i < 9; ++i)
+    if (!(equilibrium(i, 1.0, ux, uy) > 0)) return false;
+  return true;
+}
+
+int check_params(const flb_params* p) {
+  if (!p) return set_error(FLB_E_ARG, "null parameters");
+  if (p->nx < 3 || p->ny < 3) return set_error(FLB_E_ARG, "nx, ny must be >= 3");
+  if ((uint64_t)p->nx * (uint64_t)p->ny * 9ull >= (1ull << 32))
+    return set_error(FLB_E_ARG, "lattice too large (9 nx ny must fit 32 bits)");
+  if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return set_error(FLB_E_ARG, "rho0 must be > 0");
+  if (!(p->kT >= 0) || !std::isfinite(p->kT)) return set_error(FLB_E_ARG, "kT must be >= 0");
+  for (int a = 0; a < 6; ++a)
+    if (!(p->tau[a] > 0.5) || !std::isfinite(p->tau[a]))
+      return set_error(FLB_E_ARG, "tau[%d] must be > 1/2", a);
+  if (p->precision != FLB_FP64 && p->precision != FLB_FP32_SHIFTED)
+    return set_error(FLB_E_ARG, "unknown precision");
+  if (p->basis < 0 || p->basis > 2) return set_error(FLB_E_ARG, "unknown basis");
+  if (p->init < 0 || p->init > 2) return set_error(FLB_E_ARG, "unknown init");
+  if (p->sample_every < 0 || p->sk_every < 0 || p->block_steps < 0)
+    return set_error(FLB_E_ARG, "negative sampling interval");
+  if (!valid_velocity(p->ux0, p->uy0))
+    return set_error(FLB_E_INVALID_VELOCITY, "u0 = (%g, %g) outside the validity region",
+                     p->ux0, p->uy0);
+  return FLB_OK;
+}
+
+// Compute precision of the collision: FP64 storage computes in FP64; FP32
+// shifted storage computes in FP32 unless the background flow is fast, where
+// the basis construction is carried out in FP64.
+int compute_precision(const flb_params* p) {
+  if (p->precision == FLB_FP64) return 0;
+  const double u = std::sqrt(p->ux0 * p->ux0 + p->uy0 * p->uy0);
+  return u > kFp32BasisMaxSpeed ? 0 : 1;
+}
+
+void fill_slot(const flb_params* p, SlotDesc* d) {
+  d->nx = p->nx;
+  d->ny = p->ny;
+  d->tiles_x = (p->nx + kTileX - 1) / kTileX;
+  d->ntiles = d->tiles_x * ((p->ny + kTileY - 1) / kTileY);
+  d->k0 = (uint32_t)p->seed;
+  d->k1 = (uint32_t)(p->seed >> 32);
+  d->sample_every = p->sample_every;
+  d->sk_every = p->sk_every;
+  const double mu = 3.0 * p->kT;
+  d->noise = mu > 0 ? 1 : 0;
+  d->rho0 = p->rho0;
+  d->ux0 = p->ux0;
+  d->uy0 = p->uy0;
+  d->rho0f = (float)p->rho0;
+  for (int a = 0; a < 6; ++a) {
+    const double tau = p->tau[a];
+    d->rt[a] = 1.0 / tau;
+    d->xc[a] = std::sqrt(mu * (2 * tau - 1)) / tau;
+    d->rtf[a] = (float)d->rt[a];
+    d->xcf[a] = (float)d->xc[a];
+  }
+  for (int i = 0; i < 9; ++i) d->e[i] = equilibrium(i, p->rho0, p->ux0, p->uy0) - kW[i] * p->rho0;
+}
+
+// ------------------------------------------------------------ statistics
+void Stats::reset(int block_steps) {
+  tb_len = block_steps > 0 ? (uint64_t)block_steps : 0;
+  tb_fill = 0;
+  nb = 0;
+  nsamples = 0;
+  rec_len.assign(max_blocks, 0);
+}
+
+// Bookkeeping after a correlator sample of `nsites` sites was enqueued: the
+// open time block closes after tb_len samples (its partials are summed into
+// record nb and cleared); a full record list merges neighbours pairwise and
+// doubles the block length.
+hipError_t Stats::after_sample(uint64_t nsites, double* d_partials, int ntiles, double* d_records,
+                               hipStream_t st) {
+  nsamples += nsites;
+  if (tb_len == 0) return hipSuccess;
+  if (++tb_fill < tb_len) return hipSuccess;
+  if (rec_len.size() < (size_t)max_blocks) rec_len.assign(max_blocks, 0);
+  if (nb == (uint64_t)max_blocks) {
+    hipError_t e = launch_merge_blocks(d_records, max_blocks / 2, st);
+    if (e != hipSuccess) return e;
+    for (int b = 0; b < max_blocks / 2; ++b) rec_len[b] = rec_len[2 * b] + rec_len[2 * b + 1];
+    nb = max_blocks / 2;
+    tb_len *= 2;
+  }
+  hipError_t e = launch_close_block(d_partials, ntiles, d_records + nb * kNStat, st);
+  rec_len[nb] = tb_fill;
+  nb += 1;
+  tb_fill = 0;
+  return e;
+}
+
+uint64_t Stats::block_samples(uint64_t b) const { return b < rec_len.size() ? rec_len[b] : 0; }
+
+static void cov_from(const double* S, double n, double C[81]) {
+  double m[9];
+  for (int i = 0; i < 9; ++i) m[i] = S[i] / n;
+  int k = 9;
+  for (int i = 0; i < 9; ++i)
+    for (int j = i; j < 9; ++j, ++k) {
+      const double c = S[k] / n - m[i] * m[j];
+      C[i * 9 + j] = c;
+      C[j * 9 + i] = c;
+    }
+}
+
+static void transform(const double B[81], const double C[81], double out[81]) {
+  double T[81];
+  for (int a = 0; a < 9; ++a)
+    for (int j = 0; j < 9; ++j) {
+      double s = 0;
+      for (int i = 0; i < 9; ++i) s += B[a * 9 + i] * C[i * 9 + j];
+      T[a * 9 + j] = s;
+    }
+  for (int a = 0; a < 9; ++a)
+    for (int b = 0; b < 9; ++b) {
+      double s = 0;
+      for (int j = 0; j < 9; ++j) s += T[a * 9 + j] * B[b * 9 + j];
+      out[a * 9 + b] = s;
+    }
+}
+
+// Final correlators from the closed block records (nb x 54, host copy) and
+// the open partial sums (54); standard errors from the spread of the
+// per-record estimates.
+int finish_covariance(const Stats& S, const std::vector<double>& rec, const double* open,
+                      uint64_t sites, const double mt0[81], flb_cov* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->nsamples = S.nsamples;
+  out->nblocks = S.nb;
+  if (S.nsamples == 0) return FLB_OK;
+  double tot[kNStat];
+  for (int v = 0; v < kNStat; ++v) tot[v] = 0;
+  for (uint64_t b = 0; b < S.nb; ++b)
+    for (int v = 0; v < kNStat; ++v) tot[v] += rec[b * kNStat + v];
+  for (int v = 0; v < kNStat; ++v) tot[v] += open[v];
+  const double n = (double)S.nsamples;
+  for (int i = 0; i < 9; ++i) out->mean_df[i] = tot[i] / n;
+  cov_from(tot, n, out->cov_f);
+  double m[81];
+  hermite_rows(m);
+  transform(mt0, out->cov_f, out->cov_m_fnorm_u0);
+  transform(m, out->cov_f, out->cov_m_hermite);
+  if (S.nb >= 2) {
+    double sf[81] = {0}, sf2[81] = {0}, sm[81] = {0}, sm2[81] = {0};
+    for (uint64_t b = 0; b < S.nb; ++b) {
+      const double nbk = (double)S.block_samples(b) * (double)sites;
+      double Cb[81], Mb[81];
+      cov_from(&rec[b * kNStat], nbk, Cb);
+      transform(mt0, Cb, Mb);
+      for (int k = 0; k < 81; ++k) {
+        sf[k] += Cb[k];
+        sf2[k] += Cb[k] * Cb[k];
+        sm[k] += Mb[k];
+        sm2[k] += Mb[k] * Mb[k];
+      }
+    }
+    const double nb = (double)S.nb;
+    for (int k = 0; k < 81; ++k) {
+      const double vf = (sf2[k] - sf[k] * sf[k] / nb) / (nb - 1);
+      const double vm = (sm2[k] - sm[k] * sm[k] / nb) / (nb - 1);
+      out->se_cov_f[k] = std::sqrt(vf > 0 ? vf / nb : 0.0);
+      out->se_cov_m[k] = std::sqrt(vm > 0 ? vm / nb : 0.0);
+    }
+  } else {
+    for (int k = 0; k < 81; ++k) out->se_cov_f[k] = out->se_cov_m[k] = NAN;
+  }
+  return FLB_OK;
+}
+
+}  // namespace flb
+
+extern "C" const char* flb_last_error(void) { return flb::g_err.c_str(); }

@@ -1,0 +1,71 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every entry point include/flb.h declares, and its ctypes structures match
+the header's layout.  No compute calls (no GPU here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "flb.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|size_t|uint64_t|int64_t|void|char)\s*\**\s*"
+                       r"(flb_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("flb_lattice_create", "flb_lattice_step", "flb_lattice_read_moments",
+                 "flb_lattice_read_covariance", "flb_ensemble_step", "flb_server_submit"):
+        assert must in names
+    assert len(names) >= 40
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1204_6734_amd as F
+    lib = F.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts():
+    import paper_1204_6734_amd as F
+    # flb_params: 2 int32, 4 doubles, 6 doubles, uint64, 6 int32
+    assert C.sizeof(F.Params) == 8 + 8 * 4 + 8 * 6 + 8 + 4 * 6
+    assert F.Params.tau.offset == 40 and F.Params.seed.offset == 88
+    assert C.sizeof(F.Cov) == 16 + 8 * (9 + 81 * 5)
+    assert F.Result.cov.offset == 56
+
+
+def test_create_without_gpu_fails_cleanly():
+    import paper_1204_6734_amd as F
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("GPU present")
+    except Exception:
+        pass
+    with pytest.raises(F.FlbError) as e:
+        F.Lattice(F.make_params(16, 16))
+    assert e.value.code in (F.E_OOM, F.E_HIP)
+
+
+def test_argument_errors_are_reported():
+    import paper_1204_6734_amd as F
+    lib = F.load()
+    bad = [F.make_params(2, 16), F.make_params(16, 16, tau=(0.5,) * 6),
+           F.make_params(16, 16, kT=-1.0), F.make_params(16, 16, ux0=0.5, uy0=0.5)]
+    codes = []
+    for p in bad:
+        h = C.c_void_p()
+        codes.append(lib.flb_lattice_create(C.byref(p), None, C.byref(h)))
+        assert lib.flb_last_error()
+    assert codes[:3] == [F.E_ARG] * 3 and codes[3] == F.E_INVALID_VELOCITY
+    assert lib.flb_lattice_bytes(C.byref(bad[0])) == 0
+    assert lib.flb_lattice_bytes(C.byref(F.make_params(64, 64))) > 9 * 64 * 64 * 4

@@ -1,0 +1,80 @@
+"""Parity at the measured sizes, in the launch configuration the benchmark
+times: the 8192 x 8192 FP32-shifted lattice (background u_x0 = 0.1,
+kT = 1e-4, transverse shear wave) and the 256 x 256 FP64 lattice.  The
+oracle cannot run these whole; it recomputes sampled sites one by one
+(each post-streaming population at x is the oracle collision of the
+pre-step state at x - v_i), at both streaming phases, and properties that
+hold at any size are checked on the whole lattice."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1204_6734_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+VX, VY, _ = O.velocities()
+
+
+def one_step_samples(p_oracle, f_before, t, sites, nx, ny):
+    """Oracle value of f_i(x, t+1) = collide(f(x - v_i, t))_i for sampled x."""
+    out = np.empty((len(sites), 9))
+    for k, (x, y) in enumerate(sites):
+        for i in range(9):
+            xs, ys = (x - VX[i]) % nx, (y - VY[i]) % ny
+            fo = O.collide(p_oracle, f_before[:, ys, xs], site=ys * nx + xs, step=t)
+            out[k, i] = fo[i]
+    return out
+
+
+def check_sampled(F, prec, nx, ny, ux0, tol, nsample, tau=(1.0,) * 6):
+    kw = dict(ux0=ux0, kT=1e-4, tau=tau, seed=1)
+    L = F.Lattice(F.make_params(nx, ny, precision=prec, init=2, **kw))
+    L.set_fields(*I.shear_wave_fields(nx, ny, ux0=ux0, amp=1e-3))
+    po = O.make_params(nx, ny, **kw)
+    rng = np.random.default_rng(0)
+    sites = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1)]
+    sites += [(int(a), int(b)) for a, b in zip(rng.integers(0, nx, nsample),
+                                               rng.integers(0, ny, nsample))]
+    L.step(3)
+    for _ in range(2):  # odd phase, then even phase
+        t = L.t
+        f0 = L.populations()
+        L.step(1)
+        f1 = L.populations()
+        want = one_step_samples(po, f0, t, sites, nx, ny)
+        got = np.array([f1[:, y, x] for (x, y) in sites])
+        err = np.abs(got - want).max()
+        assert err <= tol, (t, err)
+        del f0, f1
+
+
+def test_8192_fp32_sampled_sites(flb):
+    check_sampled(flb, flb.FP32_SHIFTED, 8192, 8192, 0.1, tol=2e-7, nsample=64)
+
+
+def test_256_fp64_sampled_sites(flb):
+    check_sampled(flb, flb.FP64, 256, 256, 0.2, tol=1e-14, nsample=200, tau=I.mixed_taus(2))
+
+
+def test_8192_fp32_shear_wave_decay_and_conservation(flb):
+    """Noise-free: j_y(k = 2 pi/L) decays as exp(-nu k^2 t), nu = (tau-1/2)/3,
+    and advects with u_x0 (phase -k u_x0 t); mass and momentum are conserved."""
+    nx = ny = 8192
+    L = flb.Lattice(flb.make_params(nx, ny, precision=flb.FP32_SHIFTED, ux0=0.1, kT=0.0, init=2))
+    L.set_fields(*I.shear_wave_fields(nx, ny, ux0=0.1, amp=1e-3))
+    a0 = L.fourier_mode(2, 1, 0)
+    m0 = [L.fourier_mode(w, 0, 0) for w in range(3)]
+    t = 1000
+    L.step(t)
+    a1 = L.fourier_mode(2, 1, 0)
+    k = 2 * math.pi / nx
+    nu = 0.5 / 3
+    ratio = abs(a1) / abs(a0)
+    assert abs(ratio / math.exp(-nu * k * k * t) - 1) < 2e-5
+    dphase = np.angle(a1 / a0 * np.exp(1j * k * 0.1 * t))
+    assert abs(dphase) < 1e-4
+    m1 = [L.fourier_mode(w, 0, 0) for w in range(3)]
+    for a, b in zip(m0, m1):
+        assert abs(a - b) <= 1e-6 * nx * ny

@@ -1,0 +1,101 @@
+"""GPU tests of the batched execution patterns: ensembles in one launch
+(eager and hipGraph replay) and the continuous-batching server.  Each
+replica or request must give the same result as running it alone."""
+import numpy as np
+import pytest
+
+from paper_1204_6734_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def members(F, n, nx, ny, prec, **extra):
+    out = []
+    for m in I.ensemble_members(n, seed=3):
+        out.append(F.make_params(nx, ny, precision=prec, ux0=m["ux0"], kT=m["kT"],
+                                 seed=m["seed"], **extra))
+    return out
+
+
+@pytest.mark.parametrize("chunk", [0, 8])
+def test_ensemble_replicas_equal_alone(flb, chunk):
+    ps = members(flb, 5, 70, 20, flb.FP32_SHIFTED, sample_every=1, block_steps=16)
+    E = flb.Ensemble(ps, graph_chunk=chunk)
+    E.step(53)
+    for i in (0, 2, 4):
+        L = flb.Lattice(ps[i])
+        L.step(53)
+        np.testing.assert_array_equal(E.populations(i), L.populations())
+        ce, cl = E.covariance(i), L.covariance()
+        assert ce["nblocks"] == cl["nblocks"] == 3
+        np.testing.assert_array_equal(ce["cov_f"], cl["cov_f"])
+        np.testing.assert_array_equal(ce["se_cov_f"], cl["se_cov_f"])
+
+
+def test_ensemble_graph_replay_equals_eager(flb):
+    ps = members(flb, 4, 128, 128, flb.FP32_SHIFTED, sample_every=1, block_steps=40)
+    a = flb.Ensemble(ps, graph_chunk=20)
+    b = flb.Ensemble(ps, graph_chunk=0)
+    for _ in range(3):  # replays interleaved with eager work and syncs
+        a.step(60)
+        b.step(60)
+        a.sync()
+        b.sync()
+        for i in range(4):
+            np.testing.assert_array_equal(a.populations(i), b.populations(i))
+            np.testing.assert_array_equal(a.covariance(i)["cov_f"], b.covariance(i)["cov_f"])
+
+
+def _serve(F, reqs, budget, slots=8, chunk=50):
+    S = F.Server(budget, max_slots=slots, chunk_steps=chunk, threaded=False)
+    ids = {}
+    for k, (p, n) in enumerate(reqs):
+        ids[S.submit(p, n, tag=k)] = k
+    S.drain()
+    res = {r["tag"]: r for r in S.poll(len(reqs) + 4)}
+    S.close()
+    assert len(res) == len(reqs)
+    return res
+
+
+def test_server_result_alone_equals_in_mix(flb):
+    reqs = []
+    for k, (side, n, kT, ux) in enumerate([(64, 180, 1e-4, 0.1), (100, 75, 1e-3, 0.0),
+                                          (37, 333, 1e-5, 0.2), (64, 50, 2e-4, 0.05),
+                                          (90, 260, 5e-4, 0.15), (128, 120, 1e-4, 0.12)]):
+        p = flb.make_params(side, side, ux0=ux, kT=kT, seed=100 + k, sample_every=1,
+                            block_steps=20)
+        reqs.append((p, n))
+    # small budget and few slots: requests queue, join and leave mid-stream
+    budget = 3 * flb.Server.request_bytes(reqs[-1][0])
+    mix = _serve(flb, reqs, budget, slots=3, chunk=40)
+    for k, (p, n) in enumerate(reqs):
+        alone = _serve(flb, [(p, n)], budget, slots=1, chunk=40)[0]
+        m = mix[k]
+        assert m["status"] == 0 and alone["status"] == 0
+        assert m["cov"]["nsamples"] == n * p.nx * p.ny
+        np.testing.assert_array_equal(m["cov"]["cov_f"], alone["cov"]["cov_f"])
+        np.testing.assert_array_equal(m["cov"]["mean_df"], alone["cov"]["mean_df"])
+
+
+def test_server_matches_lattice(flb):
+    p = flb.make_params(80, 48, ux0=0.1, kT=1e-4, seed=42, sample_every=1, block_steps=25)
+    r = _serve(flb, [(p, 150)], 64 << 20)[0]
+    L = flb.Lattice(p)
+    L.step(150)
+    c = L.covariance()
+    np.testing.assert_array_equal(r["cov"]["cov_f"], c["cov_f"])
+
+
+def test_threaded_server_completes_everything(flb):
+    S = flb.Server(256 << 20, max_slots=4, chunk_steps=25, threaded=True)
+    for k in range(10):
+        p = flb.make_params(32 + 8 * k, 40, ux0=0.01 * k, kT=1e-4, seed=k, sample_every=1)
+        S.submit(p, 30 + 10 * k, tag=k)
+    S.drain()
+    res = S.poll(32)
+    assert sorted(r["tag"] for r in res) == list(range(10))
+    assert all(r["status"] == 0 for r in res)
+    assert all(r["t_submit"] <= r["t_admit"] <= r["t_done"] for r in res)
+    st = S.stats()
+    assert st["completed"] == 10 and st["queued"] == 0
