@@ -117,6 +117,20 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
             "dtype": "f32", "kernel_name": "step_fp32_8192"}
 
 
+def copy_calibration(reps: int = 5):
+    """A plain copy kernel of known size: each launch reads and writes
+    exactly 1 GiB.  Its FETCH_SIZE / WRITE_SIZE readings scale the step
+    kernel's counters to bytes."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,7 +140,12 @@ def main():
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
                                    "decomposition is a design, not part of this build",

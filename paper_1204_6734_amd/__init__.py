@@ -120,6 +120,13 @@ def load(path: str | None = None):
     global _lib
     if _lib is not None:
         return _lib
+    # One HIP runtime per process: PyTorch ships its own copy of the HIP
+    # runtime under the same soname; loading torch first makes libflb bind
+    # to that copy, so torch tensors and streams and libflb share a runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"libflb.so not found at {p}: run python -m paper_1204_6734_amd.build")
