@@ -34,9 +34,17 @@ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 enum : int { kBasisFnormLocal = 0, kBasisHermite = 1, kBasisFnormLut = 2 };
 
 // ------------------------------------------------------------------------
+// Three-input XOR in one VALU instruction (gfx950 v_bitop3_b32 with truth
+// table 0x96); the key operand is wave-uniform and stays in an SGPR.
+__device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t d;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+  return d;
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 products, word shuffle, key xor; key bumped by the Weyl
-// increments between rounds.
+// increments between rounds.  The key must be wave-uniform.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -44,7 +52,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
     const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
     const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    c = make_uint4(xor3_vvs(hi1, c.y, k0), lo1, xor3_vvs(hi0, c.w, k1), lo0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -61,13 +69,16 @@ __device__ __forceinline__ void box_muller(uint32_t ua, uint32_t ub, R& n0, R& n
 template <>
 __device__ __forceinline__ void box_muller<float>(uint32_t ua, uint32_t ub, float& n0,
                                                   float& n1) {
+  // Hardware transcendentals: v_log_f32 is log2, v_sin/v_cos take the angle
+  // in revolutions, so r = sqrt(-2 ln2 log2 ua) and the angle 2 pi ub needs
+  // no range reduction (ub in (0, 1)).  On these 2^21 inputs they agree
+  // with the correctly rounded values to ~1.3e-7 (absolute, sin/cos) and
+  // ~1.2e-7 (relative, log), the same level as the library routines.
   const float fa = __fmaf_rn((float)ua, 4.76837158203125e-07f, 2.384185791015625e-07f);
-  const float fb = __fmaf_rn((float)ub, 9.5367431640625e-07f, 4.76837158203125e-07f);  // 2u
-  const float r = sqrtf(-2.0f * logf(fa));
-  float s, c;
-  sincospif(fb, &s, &c);
-  n0 = r * c;
-  n1 = r * s;
+  const float fb = __fmaf_rn((float)ub, 4.76837158203125e-07f, 2.384185791015625e-07f);
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(fa));
+  n0 = r * __builtin_amdgcn_cosf(fb);
+  n1 = r * __builtin_amdgcn_sinf(fb);
 }
 
 template <>
@@ -83,12 +94,11 @@ __device__ __forceinline__ void box_muller<double>(uint32_t ua, uint32_t ub, dou
 }
 
 template <typename R>
-__device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint64_t site,
+__device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint32_t site,
                                                uint64_t step, uint32_t tag, R N[6]) {
+  // counter (site, 0, step lo, step hi ^ tag): a lattice has < 2^32 sites
   const uint4 w = philox4x32_10(
-      make_uint4((uint32_t)site, (uint32_t)(site >> 32), (uint32_t)step,
-                 (uint32_t)(step >> 32) ^ tag),
-      k0, k1);
+      make_uint4(site, 0u, (uint32_t)step, (uint32_t)(step >> 32) ^ tag), k0, k1);
   const uint32_t u4 = (w.x & 0x7FFu) | ((w.y & 0x3FFu) << 11);
   const uint32_t u5 = (w.z & 0x7FFu) | ((w.w & 0x3FFu) << 11);
   box_muller<R>(w.x >> 11, w.y >> 11, N[0], N[1]);
@@ -96,26 +106,30 @@ __device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint64_
   box_muller<R>(u4, u5, N[4], N[5]);
 }
 
-__device__ __forceinline__ float rsqrt_t(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ float rcp_t(float x) { return __frcp_rn(x); }
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 
-// Per-lattice constants of the collision, in the compute type.
+// Per-lattice constants of the collision, in the compute type.  The stored
+// populations are h_i = f_i - f_i^0(rho0, u0): everything below works with
+// differences from that reference state so that single precision keeps its
+// relative accuracy on the small quantities (fluctuations, flow changes).
 template <typename R>
 struct CollideConst {
-  R rho0;
+  R rho0, ux0, uy0;
   R rt[6];     // 1/tau^a, a = 3..8
   R xc[6];     // sqrt(mu (2 tau^a - 1)) / tau^a: xi^a = sqrt(rho) xc^a (eq. (20))
   uint32_t k0, k1;
   int noise;   // 0 when kT == 0
 };
 
-// Hermite moments of the shifted populations h_i = f_i - w_i rho0 (the shift
-// carries no mass-free moment: sum_i m_i^a w_i = delta^a0, eq. (22)).
+// Hermite moments (rows of eq. (A3)) of the shifted populations h; the
+// moments of the reference f^0(rho0, u0) itself are rho0, rho0 u0 and the
+// equilibrium values of eq. (A5).
 template <typename R>
 struct Moments {
-  R drho, jx, jy;  // rho - rho0, j
+  R drho, jx, jy;  // rho - rho0, j - rho0 u0
   R M3, M4, M5, M6, M7, M8;
 };
 
@@ -284,25 +298,51 @@ __device__ __forceinline__ void upper_solve(const Basis<R>& B, const R v[6], R y
          B.r[0];
 }
 
-// One collision, eq. (6), on shifted populations h (in place).  Returns error
-// bits; on error h is left unchanged.
-template <typename R, int BASIS>
-__device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint64_t site,
-                                       uint64_t t) {
-  const Moments<R> m = hermite_moments(h);
-  const R rho = C.rho0 + m.drho;
-  if (!(rho > R(0)) || !(m.jx == m.jx) || !(m.jy == m.jy)) return kErrNonFinite;
-  const R inv = rcp_t(rho);
-  const R ux = m.jx * inv, uy = m.jy * inv;
-  // non-equilibrium Hermite moments d = M - M^0(rho,u), eq. (A5)
-  const R jxux = m.jx * ux, jyuy = m.jy * uy;
+// Local state of a site from its shifted populations: rho, u, u - u0 and the
+// non-equilibrium Hermite moments d = M(f) - M^0(rho,u) = M(h) - [M^0(rho,u) -
+// M^0(rho0,u0)], the bracket of eq. (A5) written in differences.
+template <typename R>
+struct LocalState {
+  Moments<R> m;
+  R rho, ux, uy, dux, duy, sx, sy;
   R d[6];
-  d[0] = m.M3 - R(1.5) * (jxux - jyuy);
-  d[1] = m.M4 - R(3) * m.jx * uy;
-  d[2] = m.M5 - R(1.5) * (jxux + jyuy);
-  d[3] = m.M6;
-  d[4] = m.M7;
-  d[5] = m.M8;
+};
+
+template <typename R>
+__device__ __forceinline__ bool local_state(const R h[9], R rho0, R ux0, R uy0,
+                                            LocalState<R>& L) {
+  L.m = hermite_moments(h);
+  const Moments<R>& m = L.m;
+  L.rho = rho0 + m.drho;
+  if (!(L.rho > R(0)) || !(m.jx == m.jx) || !(m.jy == m.jy)) return false;
+  const R inv = rcp_t(L.rho);
+  // rho (u - u0) = (j - rho0 u0) - (rho - rho0) u0: small quantities only
+  L.dux = (m.jx - m.drho * ux0) * inv;
+  L.duy = (m.jy - m.drho * uy0) * inv;
+  L.ux = ux0 + L.dux;
+  L.uy = uy0 + L.duy;
+  L.sx = L.ux + ux0;
+  L.sy = L.uy + uy0;
+  const R ex = rho0 * (L.dux * L.sx), ey = rho0 * (L.duy * L.sy);
+  L.d[0] = m.M3 - R(1.5) * (m.drho * (L.ux * L.ux - L.uy * L.uy) + (ex - ey));
+  L.d[1] = m.M4 - R(3) * (m.drho * (L.ux * L.uy) + rho0 * (L.dux * L.uy + ux0 * L.duy));
+  L.d[2] = m.M5 - R(1.5) * (m.drho * (L.ux * L.ux + L.uy * L.uy) + (ex + ey));
+  L.d[3] = m.M6;
+  L.d[4] = m.M7;
+  L.d[5] = m.M8;
+  return true;
+}
+
+// One collision, eq. (6), on shifted populations h (in place).  Returns
+// error bits; on error h is left unchanged.
+template <typename R, int BASIS>
+__device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_t site,
+                                       uint64_t t) {
+  LocalState<R> S;
+  if (!local_state(h, C.rho0, C.ux0, C.uy0, S)) return kErrNonFinite;
+  const Moments<R>& m = S.m;
+  const R rho = S.rho, ux = S.ux, uy = S.uy;
+  const R* d = S.d;
 
   R N[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
   R sr = R(0);
@@ -360,15 +400,18 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint64_
   const R K = (Bx * bx + By * by) - A;
   R s[9];
   hermite_back(y, s);
-  h[0] += g[0] * (s[0] + K);
-  h[1] += g[1] * (s[1] + (K - Bx));
-  h[3] += g[3] * (s[3] + (K + Bx));
-  h[2] += g[2] * (s[2] + (K - By));
-  h[4] += g[4] * (s[4] + (K + By));
-  h[5] += g[5] * (s[5] + (K - (Bx + By)));
-  h[7] += g[7] * (s[7] + (K + (Bx + By)));
-  h[6] += g[6] * (s[6] + (K + (Bx - By)));
-  h[8] += g[8] * (s[8] + (K - (Bx - By)));
+  R tt[9];
+  tt[0] = s[0] + K;
+  tt[1] = s[1] + (K - Bx);
+  tt[3] = s[3] + (K + Bx);
+  tt[2] = s[2] + (K - By);
+  tt[4] = s[4] + (K + By);
+  tt[5] = s[5] + (K - (Bx + By));
+  tt[7] = s[7] + (K + (Bx + By));
+  tt[6] = s[6] + (K + (Bx - By));
+  tt[8] = s[8] + (K - (Bx - By));
+#pragma unroll
+  for (int i = 0; i < 9; ++i) h[i] += g[i] * tt[i];
   return 0;
 }
 

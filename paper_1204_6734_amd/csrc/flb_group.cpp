@@ -172,8 +172,9 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
     const double mu = p.init == FLB_INIT_THERMAL ? 3.0 * p.kT : 0.0;
     for (int y0 = 0; y0 < p.ny; y0 += band_rows) {
       const int rows = std::min(band_rows, p.ny - y0);
-      HIPC(launch_init(storage, pop[s], nullptr, nullptr, nullptr, p.rho0, p.ux0, p.uy0, p.nx,
-                       p.ny, mu, hdesc[s].k0, hdesc[s].k1, 0, y0, rows, st));
+      HIPC(launch_init(storage, pop[s], nullptr, nullptr, nullptr, p.rho0, p.ux0, p.uy0,
+                       slot_shift(hdesc[s]), p.nx, p.ny, mu, hdesc[s].k0, hdesc[s].k1, 0, y0, rows,
+                       st));
     }
   }
   t = 0;
@@ -219,21 +220,21 @@ int Group::after_step(uint64_t tt) {
   return FLB_OK;
 }
 
-int Group::launch_one(uint32_t k, bool sample) {
+int Group::launch_one(uint32_t k, bool sample, int odd) {
   if (profiling) {
     std::pair<hipEvent_t, hipEvent_t> ev;
     HIPC(hipEventCreate(&ev.first));
     HIPC(hipEventCreate(&ev.second));
     HIPC(hipEventRecord(ev.first, st));
-    HIPC(launch_step(storage, compute, basis, sample, d_slots, d_prefix, (int)P.size(),
+    HIPC(launch_step(storage, compute, basis, sample, odd, d_slots, d_prefix, (int)P.size(),
                      total_tiles, d_clock, k, st));
     HIPC(hipEventRecord(ev.second, st));
     events.push_back(ev);
     prof_launches += 1;
     return FLB_OK;
   }
-  HIPC(launch_step(storage, compute, basis, sample, d_slots, d_prefix, (int)P.size(), total_tiles,
-                   d_clock, k, st));
+  HIPC(launch_step(storage, compute, basis, sample, odd, d_slots, d_prefix, (int)P.size(),
+                   total_tiles, d_clock, k, st));
   return FLB_OK;
 }
 
@@ -263,8 +264,9 @@ int Group::capture_graph() {
   for (auto& p : P) sample |= p.sample_every == 1;
   HIPC(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   for (int k = 0; k < graph_chunk; ++k) {
-    hipError_t e = launch_step(storage, compute, basis, sample, d_slots, d_prefix, (int)P.size(),
-                               total_tiles, d_clock, (uint32_t)k, st);
+    // replays start at even times (see step()), so step k has parity k & 1
+    hipError_t e = launch_step(storage, compute, basis, sample, k & 1, d_slots, d_prefix,
+                               (int)P.size(), total_tiles, d_clock, (uint32_t)k, st);
     if (e != hipSuccess) {
       hipGraph_t g;
       (void)hipStreamEndCapture(st, &g);
@@ -284,7 +286,7 @@ int Group::step(uint64_t nsteps) {
   while (done < nsteps) {
     const uint64_t left = nsteps - done;
     if (graph_chunk > 0 && graph_friendly() && left >= (uint64_t)graph_chunk &&
-        steps_to_close() >= (uint64_t)graph_chunk) {
+        (t & 1) == 0 && steps_to_close() >= (uint64_t)graph_chunk) {
       int rc = capture_graph();
       if (rc != FLB_OK) return rc;
       if (profiling) {
@@ -310,12 +312,15 @@ int Group::step(uint64_t nsteps) {
     // eager chunk: up to 2^30 steps, or up to the next time-block close when
     // a graph could resume after it
     uint64_t chunk = std::min<uint64_t>(left, 1ull << 30);
-    if (graph_chunk > 0 && graph_friendly()) chunk = std::min(chunk, std::max<uint64_t>(1, steps_to_close()));
+    if (graph_chunk > 0 && graph_friendly()) {
+      chunk = std::min(chunk, std::max<uint64_t>(1, steps_to_close()));
+      if (t & 1) chunk = 1;  // realign replays to even times
+    }
     for (uint64_t k = 0; k < chunk; ++k) {
       const uint64_t tt = t + k;
       bool sample = false;
       for (int s = 0; s < n; ++s) sample |= sample_due(s, tt) || sk_due(s, tt);
-      int rc = launch_one((uint32_t)k, sample);
+      int rc = launch_one((uint32_t)k, sample, (int)(tt & 1));
       if (rc != FLB_OK) return rc;
       rc = after_step(tt);
       if (rc != FLB_OK) return rc;
@@ -362,7 +367,8 @@ int Group::read_populations(int s, double* f) {
   const size_t N = (size_t)p.nx * p.ny;
   for (int y0 = 0; y0 < p.ny; y0 += band_rows) {
     const int rows = std::min(band_rows, p.ny - y0);
-    HIPC(launch_read_state(storage, pop[s], d_io, p.nx, p.ny, (int)(t & 1), p.rho0, y0, rows, st));
+    HIPC(launch_read_state(storage, pop[s], d_io, p.nx, p.ny, (int)(t & 1), slot_shift(hdesc[s]),
+                           y0, rows, st));
     const size_t B = (size_t)rows * p.nx;
     for (int i = 0; i < 9; ++i)
       HIPC(hipMemcpyAsync(f + i * N + (size_t)y0 * p.nx, d_io + i * B, B * sizeof(double),
@@ -385,8 +391,8 @@ int Group::set_populations(int s, const double* f, uint64_t tnew) {
     for (int i = 0; i < 9; ++i)
       HIPC(hipMemcpyAsync(d_io + i * B, f + i * N + (size_t)y0 * p.nx, B * sizeof(double),
                           hipMemcpyHostToDevice, st));
-    HIPC(launch_write_state(storage, pop[s], d_io, p.nx, p.ny, (int)(t & 1), p.rho0, y0, rows,
-                            st));
+    HIPC(launch_write_state(storage, pop[s], d_io, p.nx, p.ny, (int)(t & 1), slot_shift(hdesc[s]),
+                            y0, rows, st));
     HIPC(hipStreamSynchronize(st));
   }
   return FLB_OK;
@@ -401,8 +407,9 @@ int Group::set_fields(int s, const double* rho, const double* ux, const double* 
     HIPC(hipMemcpyAsync(d_io, rho + off, B * sizeof(double), hipMemcpyHostToDevice, st));
     HIPC(hipMemcpyAsync(d_io + B, ux + off, B * sizeof(double), hipMemcpyHostToDevice, st));
     HIPC(hipMemcpyAsync(d_io + 2 * B, uy + off, B * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPC(launch_init(storage, pop[s], d_io, d_io + B, d_io + 2 * B, p.rho0, p.ux0, p.uy0, p.nx,
-                     p.ny, 0.0, hdesc[s].k0, hdesc[s].k1, (int)(t & 1), y0, rows, st));
+    HIPC(launch_init(storage, pop[s], d_io, d_io + B, d_io + 2 * B, p.rho0, p.ux0, p.uy0,
+                     slot_shift(hdesc[s]), p.nx, p.ny, 0.0, hdesc[s].k0, hdesc[s].k1,
+                     (int)(t & 1), y0, rows, st));
     HIPC(hipStreamSynchronize(st));
   }
   return FLB_OK;
@@ -426,8 +433,8 @@ int Group::read_moments(int s, int at, double* m) {
   }
   for (int y0 = 0; y0 < p.ny; y0 += band_rows) {
     const int rows = std::min(band_rows, p.ny - y0);
-    HIPC(launch_moments(storage, pop[s], B, d_io, p.nx, p.ny, (int)(t & 1), p.rho0, d_err + s,
-                        y0, rows, st));
+    HIPC(launch_moments(storage, pop[s], B, d_io, p.nx, p.ny, (int)(t & 1), p.rho0, p.ux0,
+                        p.uy0, slot_shift(hdesc[s]), d_err + s, y0, rows, st));
     const size_t Bn = (size_t)rows * p.nx;
     for (int a = 0; a < 9; ++a)
       HIPC(hipMemcpyAsync(m + a * N + (size_t)y0 * p.nx, d_io + a * Bn, Bn * sizeof(double),
@@ -475,10 +482,13 @@ int Group::read_structure_factor(int which, double* out) {
   if (rc != FLB_OK) return rc;
   if (!d_skacc) return set_error(FLB_E_STATE, "structure factors are off (sk_every = 0)");
   if (which < 0 || which > 4) return set_error(FLB_E_ARG, "unknown structure factor %d", which);
-  const size_t N = (size_t)P[0].nx * P[0].ny;
-  HIPC(hipMemcpy(out, d_skacc + which * N, N * sizeof(double), hipMemcpyDeviceToHost));
+  const int nx = P[0].nx, ny = P[0].ny;
+  const size_t N = (size_t)nx * ny;
+  std::vector<double> tmp(N);  // device order [kx][ky]
+  HIPC(hipMemcpy(tmp.data(), d_skacc + which * N, N * sizeof(double), hipMemcpyDeviceToHost));
   const double norm = nsk > 0 ? 1.0 / ((double)nsk * (double)N) : 0.0;
-  for (size_t k = 0; k < N; ++k) out[k] *= norm;
+  for (int kx = 0; kx < nx; ++kx)
+    for (int ky = 0; ky < ny; ++ky) out[(size_t)ky * nx + kx] = tmp[(size_t)kx * ny + ky] * norm;
   return FLB_OK;
 }
 
@@ -739,7 +749,7 @@ int flb_ensemble_set_graph_chunk(flb_ensemble* E, int32_t steps) {
     (void)hipGraphDestroy(E->g.graph);
     E->g.graph = nullptr;
   }
-  E->g.graph_chunk = steps;
+  E->g.graph_chunk = steps + (steps & 1);  // even: replays keep the streaming phase
   return FLB_OK;
 }
 int flb_ensemble_step(flb_ensemble* E, uint64_t n) {

@@ -69,7 +69,7 @@ struct Group {
   bool sample_due(int s, uint64_t tt) const;
   bool sk_due(int s, uint64_t tt) const;
   int after_step(uint64_t tt);
-  int launch_one(uint32_t k, bool sample);
+  int launch_one(uint32_t k, bool sample, int odd);
   bool graph_friendly() const;
   uint64_t steps_to_close() const;
   int capture_graph();

@@ -71,6 +71,8 @@ template <>
 __device__ __forceinline__ CollideConst<float> collide_const<float>(const SlotDesc& sd) {
   CollideConst<float> C;
   C.rho0 = sd.rho0f;
+  C.ux0 = sd.ux0f;
+  C.uy0 = sd.uy0f;
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
     C.rt[a] = sd.rtf[a];
@@ -86,6 +88,8 @@ template <>
 __device__ __forceinline__ CollideConst<double> collide_const<double>(const SlotDesc& sd) {
   CollideConst<double> C;
   C.rho0 = sd.rho0;
+  C.ux0 = sd.ux0;
+  C.uy0 = sd.uy0;
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
     C.rt[a] = sd.rt[a];
@@ -97,45 +101,64 @@ __device__ __forceinline__ CollideConst<double> collide_const<double>(const Slot
   return C;
 }
 
-// Sum of 54 per-lane values over a 64-lane wavefront, transposed: after six
-// butterfly passes that each halve the number of values a lane carries,
-// lane l holds the wave total of value l (values 54..63 are zero).
-__device__ __forceinline__ double wave_transpose_sum(double (&v)[64], int lane) {
+// Sums of 32 per-lane values over a 64-lane wavefront, transposed: five
+// butterfly passes each halve the number of values a lane carries and a
+// last pass adds the two lanes that share a value, after which lanes 2v and
+// 2v+1 both hold the wave total of value v.
+__device__ __forceinline__ double pick(uint64_t mask, double a, double b) {
+  // a where mask is all ones, b where it is zero (bitwise, so the choice is
+  // never turned into a dynamically indexed array access)
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  return __builtin_bit_cast(double, (ua & mask) | (ub & ~mask));
+}
+
+__device__ __forceinline__ double wave_transpose_sum32(double (&v)[32], int lane) {
 #pragma unroll
-  for (int off = 32, n = 32; off >= 1; off >>= 1, n >>= 1) {
-    const bool up = (lane & off) != 0;
+  for (int off = 32, n = 16; off >= 2; off >>= 1, n >>= 1) {
+    const uint64_t up = (lane & off) ? ~0ull : 0ull;
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-      const double send = up ? v[k] : v[k + n];
-      const double keep = up ? v[k + n] : v[k];
+      const double send = pick(up, v[k], v[k + n]);
+      const double keep = pick(up, v[k + n], v[k]);
       v[k] = keep + __shfl_xor(send, off, 64);
     }
   }
-  return v[0];
+  return v[0] + __shfl_xor(v[0], 1, 64);
 }
 
-// Correlator sums of df_i = f_i - f_i^0(rho0, u0): 9 first moments and the
-// 45 products i <= j, added to this tile's open time-block partials.
+// Correlator sums of df_i = f_i - f_i^0(rho0, u0) (= the stored h_i): 9
+// first moments and the 45 products i <= j (row-major), added to this
+// tile's open time-block partials.  Reduced in two groups of 32 values to
+// keep registers low.
 template <typename R>
 __device__ __forceinline__ void sample_correlators(const R h[9], bool active,
                                                    const SlotDesc& sd, int tile_local) {
   __shared__ double red[kTileY][kTileX];
-  double v[64];
   double df[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) df[i] = active ? (double)h[i] - sd.e[i] : 0.0;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) v[i] = df[i];
-  int k = 9;
-#pragma unroll
-  for (int i = 0; i < 9; ++i)
-#pragma unroll
-    for (int j = i; j < 9; ++j) v[k++] = df[i] * df[j];
-#pragma unroll
-  for (int q = 54; q < 64; ++q) v[q] = 0.0;
+  for (int i = 0; i < 9; ++i) df[i] = active ? (double)h[i] : 0.0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double s = wave_transpose_sum(v, lane);
-  red[wave][lane] = s;
+#pragma unroll
+  for (int group = 0; group < 2; ++group) {
+    double v[32];
+    int k = 0, q = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if (q >= group * 32 && q < group * 32 + 32) v[k++] = df[i];
+      ++q;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+      for (int j = i; j < 9; ++j) {
+        if (q >= group * 32 && q < group * 32 + 32) v[k++] = df[i] * df[j];
+        ++q;
+      }
+#pragma unroll
+    for (; k < 32; ++k) v[k] = 0.0;
+    const double tot = wave_transpose_sum32(v, lane);
+    if ((lane & 1) == 0) red[wave][group * 32 + (lane >> 1)] = tot;
+  }
   __syncthreads();
   if (threadIdx.x < kNStat) {
     const double tot = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
@@ -145,7 +168,62 @@ __device__ __forceinline__ void sample_correlators(const R h[9], bool active,
   }
 }
 
-template <typename S, typename R, int BASIS, bool SAMPLE>
+// Byte offsets (within their planes) of the nine populations a site reads
+// in phase ODD, with the plane each one lives in.  Even phase: plane i at
+// the site itself.  Odd phase: plane opp(i) at x - v_i.  After the
+// collision the value of direction kOpp[i] goes back to the same place.
+// Rows are wave-uniform (one wavefront = 64 sites of one row), so only the
+// x wrap is per lane.
+template <typename S, int ODD>
+__device__ __forceinline__ void site_offsets(int x, int y, int nx, int ny, uint32_t off[9]) {
+  constexpr uint32_t E = sizeof(S);
+  const uint32_t rc = (uint32_t)y * nx * E;
+  const uint32_t xc = (uint32_t)x * E;
+  if (!ODD) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) off[i] = rc + xc;
+  } else {
+    const uint32_t rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx * E;
+    const uint32_t rp = (uint32_t)(y == ny - 1 ? 0 : y + 1) * nx * E;
+    const uint32_t xm = x == 0 ? (uint32_t)(nx - 1) * E : xc - E;
+    const uint32_t xp = x == nx - 1 ? 0u : xc + E;
+    off[0] = rc + xc;
+    off[1] = rc + xm;  // v=( 1, 0) from (x-1, y)
+    off[2] = rm + xc;  // v=( 0, 1) from (x, y-1)
+    off[3] = rc + xp;  // v=(-1, 0) from (x+1, y)
+    off[4] = rp + xc;  // v=( 0,-1) from (x, y+1)
+    off[5] = rm + xm;  // v=( 1, 1) from (x-1, y-1)
+    off[6] = rm + xp;  // v=(-1, 1) from (x+1, y-1)
+    off[7] = rp + xp;  // v=(-1,-1) from (x+1, y+1)
+    off[8] = rp + xm;  // v=( 1,-1) from (x-1, y+1)
+  }
+}
+
+// Raw buffer access to one population plane: the 128-bit resource (base,
+// size) is wave-uniform and lives in SGPRs, the per-lane byte offset is a
+// 32-bit VGPR, so no per-lane 64-bit address arithmetic is needed.  An
+// offset outside the plane reads zero and drops the store.
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(void* pop, uint32_t N, int k) {
+  char* base = reinterpret_cast<char*>(pop) + (size_t)k * N * sizeof(S);
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, N * (uint32_t)sizeof(S), 0x00020000);
+}
+
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+template <typename S, typename R, int BASIS, bool SAMPLE, int ODD>
 __global__ __launch_bounds__(kBlock) void step_kernel(const SlotDesc* __restrict__ slots,
                                                       const int* __restrict__ prefix,
                                                       int nslots,
@@ -159,18 +237,19 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const SlotDesc* __restrict
   const int lt = tile - prefix[s];
   const int nx = sd.nx, ny = sd.ny;
   const int ty = lt / sd.tiles_x, tx = lt - ty * sd.tiles_x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = tx * kTileX + (threadIdx.x & (kTileX - 1));
-  const int y = ty * kTileY + (threadIdx.x >> 6);
+  const int y = ty * kTileY + wave;
   const bool active = (x < nx) && (y < ny);
   const uint32_t N = (uint32_t)nx * (uint32_t)ny;
-  S* __restrict__ pop = (S*)sd.pop;
 
-  uint32_t idx[9];
+  uint32_t off[9];
   R h[9];
   if (active) {
-    site_indices(x, y, nx, ny, (int)(t & 1), N, idx);
+    site_offsets<S, ODD>(x, y, nx, ny, off);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) h[i] = (R)pop[idx[i]];
+    for (int i = 0; i < 9; ++i)
+      h[i] = (R)buf_load(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), off[i], (S*)nullptr);
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) h[i] = R(0);
@@ -180,30 +259,30 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const SlotDesc* __restrict
     if (sd.sample_every > 0 && t % (uint64_t)sd.sample_every == 0)
       sample_correlators<R>(h, active, sd, lt);
     if (sd.skf != nullptr && sd.sk_every > 0 && t % (uint64_t)sd.sk_every == 0 && active) {
-      // structure-factor fields in the f-norm at (rho0, u0): d rho,
-      // dj~_x = sqrt3 (j_x - u_x0 rho), dj~_y = sqrt3 (j_y - u_y0 rho)  (eq. (34))
+      // structure-factor fields in the f-norm at (rho0, u0): d rho and
+      // dj~ = sqrt3 (j - u0 rho) = sqrt3 ((j - rho0 u0) - u0 (rho - rho0))  (eq. (34))
       double hd[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) hd[i] = (double)h[i];
       const Moments<double> m = hermite_moments(hd);
-      const double rho = sd.rho0 + m.drho;
       const uint32_t site = (uint32_t)y * nx + x;
       sd.skf[site] = m.drho;
-      sd.skf[N + site] = 1.7320508075688772935 * (m.jx - sd.ux0 * rho);
-      sd.skf[2u * N + site] = 1.7320508075688772935 * (m.jy - sd.uy0 * rho);
+      sd.skf[N + site] = 1.7320508075688772935 * (m.jx - sd.ux0 * m.drho);
+      sd.skf[2u * N + site] = 1.7320508075688772935 * (m.jy - sd.uy0 * m.drho);
     }
   }
 
   if (!active) return;
   const CollideConst<R> C = collide_const<R>(sd);
-  const uint64_t site = (uint64_t)y * (uint64_t)nx + (uint64_t)x;
+  const uint32_t site = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
   const int e = collide<R, BASIS>(h, C, site, t);
   if (e) {
     atomicOr(sd.err, e);
     atomicMin(sd.err_step, (unsigned long long)t);
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) pop[idx[i]] = (S)h[kOpp[i]];
+  for (int i = 0; i < 9; ++i)
+    buf_store(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), off[i], (S)h[kOpp[i]]);
 }
 
 __global__ void tick_kernel(uint64_t* clock, uint64_t n) { *clock += n; }
@@ -213,33 +292,29 @@ __global__ void tick_kernel(uint64_t* clock, uint64_t n) { *clock += n; }
 // `odd` (odd: the reversed, un-streamed layout the next odd step reads).
 template <typename S>
 __global__ void write_state_kernel(S* pop, const double* __restrict__ f, int nx, int ny,
-                                   int odd, double rho0, int y0, int rows) {
+                                   int odd, Shift9 sh, int y0, int rows) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
   if (x >= nx) return;
   const uint32_t B = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
-  constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
   uint32_t idx[9];
   site_indices(x, y, nx, ny, odd, N, idx);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) pop[idx[i]] = (S)(f[i * (size_t)B + bs] - w[i] * rho0);
+  for (int i = 0; i < 9; ++i) pop[idx[i]] = (S)(f[i * (size_t)B + bs] - sh.v[i]);
   (void)site;
 }
 
 template <typename S>
 __global__ void read_state_kernel(const S* __restrict__ pop, double* f, int nx, int ny, int odd,
-                                  double rho0, int y0, int rows) {
+                                  Shift9 sh, int y0, int rows) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
   if (x >= nx) return;
   const uint32_t B = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
-  constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
   uint32_t idx[9];
   site_indices(x, y, nx, ny, odd, N, idx);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i * (size_t)B + bs] = (double)pop[idx[i]] + w[i] * rho0;
+  for (int i = 0; i < 9; ++i) f[i * (size_t)B + bs] = (double)pop[idx[i]] + sh.v[i];
   (void)site;
 }
 
@@ -269,14 +344,12 @@ __global__ void raw_state_kernel(S* pop, S* buf, int nx, int ny, int odd, int to
 template <typename S>
 __global__ void init_kernel(S* pop, const double* __restrict__ rho, const double* __restrict__ ux,
                             const double* __restrict__ uy, double rho0, double ux0, double uy0,
-                            int nx, int ny, double mu, uint32_t k0, uint32_t k1, int odd,
-                            int y0, int rows) {
+                            Shift9 sh, int nx, int ny, double mu, uint32_t k0, uint32_t k1,
+                            int odd, int y0, int rows) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
   if (x >= nx) return;
   const uint32_t bs = (uint32_t)blockIdx.y * nx + x;  // index into band fields
   (void)rows;
-  constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
   const double r = rho ? rho[bs] : rho0;
   const double vx = ux ? ux[bs] : ux0, vy = uy ? uy[bs] : uy0;
@@ -296,7 +369,7 @@ __global__ void init_kernel(S* pop, const double* __restrict__ rho, const double
   for (int i = 0; i < 9; ++i) {
     const double f0 = r * g[i];
     const double f = mu > 0.0 ? f0 + sqrt(mu * f0) * n9[i] : f0;
-    pop[idx[i]] = (S)(f - w[i] * rho0);
+    pop[idx[i]] = (S)(f - sh.v[i]);
   }
 }
 
@@ -305,21 +378,19 @@ __global__ void init_kernel(S* pop, const double* __restrict__ rho, const double
 // velocity), M~^{3..8} = L^-1 d.
 template <typename S>
 __global__ void moments_kernel(const S* __restrict__ pop, const double* __restrict__ B,
-                               double* out, int nx, int ny, int odd, double rho0, int* err,
-                               int y0, int rows) {
+                               double* out, int nx, int ny, int odd, double rho0, double ux0,
+                               double uy0, Shift9 sh, int* err, int y0, int rows) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
   if (x >= nx) return;
   const uint32_t Bn = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
-  constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
+  const uint32_t N = (uint32_t)nx * ny;
   uint32_t idx[9];
   site_indices(x, y, nx, ny, odd, N, idx);
   double h[9], f[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     h[i] = (double)pop[idx[i]];
-    f[i] = h[i] + w[i] * rho0;
+    f[i] = h[i] + sh.v[i];
   }
   if (B) {
     for (int a = 0; a < 9; ++a) {
@@ -329,25 +400,24 @@ __global__ void moments_kernel(const S* __restrict__ pop, const double* __restri
     }
     return;
   }
-  const Moments<double> m = hermite_moments(h);
-  const double rho = rho0 + m.drho, ux = m.jx / rho, uy = m.jy / rho;
+  LocalState<double> L;
+  if (!local_state(h, rho0, ux0, uy0, L)) {
+    atomicOr(err, kErrNonFinite);
+    return;
+  }
   double g[9];
-  unit_equilibrium(ux, uy, g);
+  unit_equilibrium(L.ux, L.uy, g);
   double gmin = g[0];
   for (int i = 1; i < 9; ++i) gmin = fmin(gmin, g[i]);
   if (!(gmin > 0.0)) atomicOr(err, kErrInvalidVelocity);
   Basis<double> Bs;
-  fnorm_basis(ux, uy, Bs);
-  const double jxux = m.jx * ux, jyuy = m.jy * uy;
-  double d[6] = {m.M3 - 1.5 * (jxux - jyuy), m.M4 - 3.0 * m.jx * uy,
-                 m.M5 - 1.5 * (jxux + jyuy), m.M6, m.M7, m.M8};
+  fnorm_basis(L.ux, L.uy, Bs);
   double Mt[6];
-  lower_solve(Bs, d, Mt);
-  out[bs] = rho;
+  lower_solve(Bs, L.d, Mt);
+  out[bs] = L.rho;
   out[Bn + bs] = 0.0;
   out[2 * (size_t)Bn + bs] = 0.0;
   for (int a = 0; a < 6; ++a) out[(3 + a) * (size_t)Bn + bs] = Mt[a];
-  (void)site;
 }
 
 // Partial sums of one Fourier coefficient sum_x dA(x) e^{-i k.x} per block.
@@ -366,10 +436,10 @@ __global__ void fourier_mode_kernel(const S* __restrict__ pop, double2* partial,
     double h[9];
     for (int i = 0; i < 9; ++i) h[i] = (double)pop[idx[i]];
     const Moments<double> m = hermite_moments(h);
-    const double rho = rho0 + m.drho;
     double a = m.drho;
-    if (which == 1) a = 1.7320508075688772935 * (m.jx - ux0 * rho);
-    if (which == 2) a = 1.7320508075688772935 * (m.jy - uy0 * rho);
+    if (which == 1) a = 1.7320508075688772935 * (m.jx - ux0 * m.drho);
+    if (which == 2) a = 1.7320508075688772935 * (m.jy - uy0 * m.drho);
+    (void)rho0;
     const long long px = ((long long)kx * x) % nx, py = ((long long)ky * y) % ny;
     const double ph = 2.0 * ((double)px / nx + (double)py / ny);
     double sn, cs;
@@ -510,9 +580,10 @@ __global__ void transpose_kernel(const double2* __restrict__ in, double2* out, i
 }
 
 // Accumulate |d rho(k)|^2, |dj~_x(k)|^2, |dj~_y(k)|^2 and dj~_x(k) dj~_y(-k)
-// from the transformed packed fields (stored transposed: [kx][ky]).  With
-// z1 = a + i b for real a, b: a(k) = (Z1(k) + conj Z1(-k))/2,
-// b(k) = (Z1(k) - conj Z1(-k))/(2i).
+// from the transformed packed fields, both stored transposed ([kx][ky]):
+// the accumulators keep that order so that consecutive threads touch
+// consecutive addresses.  With z1 = a + i b for real a, b:
+// a(k) = (Z1(k) + conj Z1(-k))/2, b(k) = (Z1(k) - conj Z1(-k))/(2i).
 __global__ void sk_accumulate_kernel(const double2* __restrict__ Zt, double* acc, int nx,
                                      int ny) {
   const uint32_t N = (uint32_t)nx * ny;
@@ -524,51 +595,65 @@ __global__ void sk_accumulate_kernel(const double2* __restrict__ Zt, double* acc
   const double2 c = Zt[N + i];
   const double ar = 0.5 * (z.x + zm.x), ai = 0.5 * (z.y - zm.y);
   const double br = 0.5 * (z.y + zm.y), bi = -0.5 * (z.x - zm.x);
-  const uint32_t o = (uint32_t)ky * nx + kx;
-  acc[o] += ar * ar + ai * ai;
-  acc[N + o] += br * br + bi * bi;
-  acc[2u * N + o] += c.x * c.x + c.y * c.y;
-  acc[3u * N + o] += br * c.x + bi * c.y;   // Re(b conj c)
-  acc[4u * N + o] += bi * c.x - br * c.y;   // Im(b conj c)
+  acc[i] += ar * ar + ai * ai;
+  acc[N + i] += br * br + bi * bi;
+  acc[2u * N + i] += c.x * c.x + c.y * c.y;
+  acc[3u * N + i] += br * c.x + bi * c.y;   // Re(b conj c)
+  acc[4u * N + i] += bi * c.x - br * c.y;   // Im(b conj c)
 }
 
 // ------------------------------------------------------------ launchers
 template <typename S, typename R, int BASIS>
-static hipError_t launch_step_t(bool sample, const SlotDesc* d_slots, const int* d_prefix,
-                                int nslots, int total_tiles, const uint64_t* d_clock,
-                                uint32_t step_idx, hipStream_t st) {
+static hipError_t launch_step_t(bool sample, int odd, const SlotDesc* d_slots,
+                                const int* d_prefix, int nslots, int total_tiles,
+                                const uint64_t* d_clock, uint32_t step_idx, hipStream_t st) {
   if (total_tiles <= 0) return hipSuccess;
-  if (sample)
-    hipLaunchKernelGGL((step_kernel<S, R, BASIS, true>), dim3(total_tiles), dim3(kBlock), 0, st,
-                       d_slots, d_prefix, nslots, d_clock, step_idx);
-  else
-    hipLaunchKernelGGL((step_kernel<S, R, BASIS, false>), dim3(total_tiles), dim3(kBlock), 0,
-                       st, d_slots, d_prefix, nslots, d_clock, step_idx);
+  const dim3 g(total_tiles), b(kBlock);
+  if (sample) {
+    if (odd)
+      hipLaunchKernelGGL((step_kernel<S, R, BASIS, true, 1>), g, b, 0, st, d_slots, d_prefix,
+                         nslots, d_clock, step_idx);
+    else
+      hipLaunchKernelGGL((step_kernel<S, R, BASIS, true, 0>), g, b, 0, st, d_slots, d_prefix,
+                         nslots, d_clock, step_idx);
+  } else {
+    if (odd)
+      hipLaunchKernelGGL((step_kernel<S, R, BASIS, false, 1>), g, b, 0, st, d_slots, d_prefix,
+                         nslots, d_clock, step_idx);
+    else
+      hipLaunchKernelGGL((step_kernel<S, R, BASIS, false, 0>), g, b, 0, st, d_slots, d_prefix,
+                         nslots, d_clock, step_idx);
+  }
   return hipGetLastError();
 }
 
 template <typename S, typename R>
-static hipError_t launch_step_b(int basis, bool sample, const SlotDesc* a, const int* b, int c,
-                                int d, const uint64_t* e, uint32_t f, hipStream_t g) {
+static hipError_t launch_step_b(int basis, bool sample, int odd, const SlotDesc* a, const int* b,
+                                int c, int d, const uint64_t* e, uint32_t f, hipStream_t g) {
   switch (basis) {
-    case kBasisFnormLocal: return launch_step_t<S, R, kBasisFnormLocal>(sample, a, b, c, d, e, f, g);
-    case kBasisHermite: return launch_step_t<S, R, kBasisHermite>(sample, a, b, c, d, e, f, g);
-    case kBasisFnormLut: return launch_step_t<S, R, kBasisFnormLut>(sample, a, b, c, d, e, f, g);
+    case kBasisFnormLocal:
+      return launch_step_t<S, R, kBasisFnormLocal>(sample, odd, a, b, c, d, e, f, g);
+    case kBasisHermite:
+      return launch_step_t<S, R, kBasisHermite>(sample, odd, a, b, c, d, e, f, g);
+    case kBasisFnormLut:
+      return launch_step_t<S, R, kBasisFnormLut>(sample, odd, a, b, c, d, e, f, g);
   }
   return hipErrorInvalidValue;
 }
 
-// storage: 0 = FP64, 1 = FP32 shifted; compute: 0 = FP64, 1 = FP32.
-hipError_t launch_step(int storage, int compute, int basis, bool sample, const SlotDesc* d_slots,
-                       const int* d_prefix, int nslots, int total_tiles,
-                       const uint64_t* d_clock, uint32_t step_idx, hipStream_t st) {
+// storage: 0 = FP64, 1 = FP32 shifted; compute: 0 = FP64, 1 = FP32; odd: the
+// streaming phase, which every slot of the launch shares (own time parity).
+hipError_t launch_step(int storage, int compute, int basis, bool sample, int odd,
+                       const SlotDesc* d_slots, const int* d_prefix, int nslots,
+                       int total_tiles, const uint64_t* d_clock, uint32_t step_idx,
+                       hipStream_t st) {
   if (storage == 0)
-    return launch_step_b<double, double>(basis, sample, d_slots, d_prefix, nslots, total_tiles,
-                                         d_clock, step_idx, st);
+    return launch_step_b<double, double>(basis, sample, odd, d_slots, d_prefix, nslots,
+                                         total_tiles, d_clock, step_idx, st);
   if (compute == 0)
-    return launch_step_b<float, double>(basis, sample, d_slots, d_prefix, nslots, total_tiles,
-                                        d_clock, step_idx, st);
-  return launch_step_b<float, float>(basis, sample, d_slots, d_prefix, nslots, total_tiles,
+    return launch_step_b<float, double>(basis, sample, odd, d_slots, d_prefix, nslots,
+                                        total_tiles, d_clock, step_idx, st);
+  return launch_step_b<float, float>(basis, sample, odd, d_slots, d_prefix, nslots, total_tiles,
                                      d_clock, step_idx, st);
 }
 
@@ -582,24 +667,24 @@ static dim3 row_grid(int nx, int rows) { return dim3((nx + 255) / 256, rows); }
 // The row-parallel utility kernels below process the band of rows
 // [y0, y0 + rows); their host-side arrays hold that band only.
 hipError_t launch_write_state(int storage, void* pop, const double* f, int nx, int ny, int odd,
-                              double rho0, int y0, int rows, hipStream_t st) {
+                              const Shift9& sh, int y0, int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(write_state_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
-                       (double*)pop, f, nx, ny, odd, rho0, y0, rows);
+                       (double*)pop, f, nx, ny, odd, sh, y0, rows);
   else
     hipLaunchKernelGGL(write_state_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
-                       (float*)pop, f, nx, ny, odd, rho0, y0, rows);
+                       (float*)pop, f, nx, ny, odd, sh, y0, rows);
   return hipGetLastError();
 }
 
 hipError_t launch_read_state(int storage, const void* pop, double* f, int nx, int ny, int odd,
-                             double rho0, int y0, int rows, hipStream_t st) {
+                             const Shift9& sh, int y0, int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(read_state_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
-                       (const double*)pop, f, nx, ny, odd, rho0, y0, rows);
+                       (const double*)pop, f, nx, ny, odd, sh, y0, rows);
   else
     hipLaunchKernelGGL(read_state_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
-                       (const float*)pop, f, nx, ny, odd, rho0, y0, rows);
+                       (const float*)pop, f, nx, ny, odd, sh, y0, rows);
   return hipGetLastError();
 }
 
@@ -615,27 +700,29 @@ hipError_t launch_raw_state(int storage, void* pop, void* buf, int nx, int ny, i
 }
 
 hipError_t launch_init(int storage, void* pop, const double* rho, const double* ux,
-                       const double* uy, double rho0, double ux0, double uy0, int nx, int ny,
-                       double mu, uint32_t k0, uint32_t k1, int odd, int y0, int rows,
-                       hipStream_t st) {
+                       const double* uy, double rho0, double ux0, double uy0, const Shift9& sh,
+                       int nx, int ny, double mu, uint32_t k0, uint32_t k1, int odd, int y0,
+                       int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(init_kernel<double>, row_grid(nx, rows), dim3(256), 0, st, (double*)pop,
-                       rho, ux, uy, rho0, ux0, uy0, nx, ny, mu, k0, k1, odd, y0, rows);
+                       rho, ux, uy, rho0, ux0, uy0, sh, nx, ny, mu, k0, k1, odd, y0, rows);
   else
     hipLaunchKernelGGL(init_kernel<float>, row_grid(nx, rows), dim3(256), 0, st, (float*)pop,
-                       rho, ux, uy, rho0, ux0, uy0, nx, ny, mu, k0, k1, odd, y0, rows);
+                       rho, ux, uy, rho0, ux0, uy0, sh, nx, ny, mu, k0, k1, odd, y0, rows);
   return hipGetLastError();
 }
 
 hipError_t launch_moments(int storage, const void* pop, const double* B, double* out, int nx,
-                          int ny, int odd, double rho0, int* err, int y0, int rows,
-                          hipStream_t st) {
+                          int ny, int odd, double rho0, double ux0, double uy0,
+                          const Shift9& sh, int* err, int y0, int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(moments_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
-                       (const double*)pop, B, out, nx, ny, odd, rho0, err, y0, rows);
+                       (const double*)pop, B, out, nx, ny, odd, rho0, ux0, uy0, sh, err, y0,
+                       rows);
   else
     hipLaunchKernelGGL(moments_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
-                       (const float*)pop, B, out, nx, ny, odd, rho0, err, y0, rows);
+                       (const float*)pop, B, out, nx, ny, odd, rho0, ux0, uy0, sh, err, y0,
+                       rows);
   return hipGetLastError();
 }
 

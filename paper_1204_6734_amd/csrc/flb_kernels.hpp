@@ -17,7 +17,7 @@ enum : int { kErrInvalidVelocity = 1, kErrNonFinite = 2 };
 // One lattice ("slot") as seen by the batched step kernel.  All slots of a
 // launch share the storage and compute types and the basis variant.
 struct SlotDesc {
-  void* pop;            // storage [9][ny][nx], shifted h = f - w rho0
+  void* pop;            // storage [9][ny][nx], shifted h = f - f^0(rho0, u0)
   double* partials;     // [ntiles][kNStat] open time-block sums (sampling)
   double* skf;          // [3][ny][nx] structure-factor fields or null
   int* err;             // error bits (atomicOr)
@@ -32,8 +32,16 @@ struct SlotDesc {
   int pad_;
   double rho0, ux0, uy0;
   double rt[6], xc[6];  // 1/tau, noise coefficients
-  double e[9];          // f_i^0(rho0,u0) - w_i rho0 (sampling reference)
-  float rho0f, rtf[6], xcf[6], padf_;  // single-precision copies
+  double shift[9];      // f_i^0(rho0, u0): storage holds h = f - shift
+  float rho0f, ux0f, uy0f, padf_;  // single-precision copies
+  float rtf[6], xcf[6], shiftf[9];
 };
 
+}  // namespace flb
+
+namespace flb {
+// Nine FP64 values passed by value to utility kernels (the storage shift).
+struct Shift9 {
+  double v[9];
+};
 }  // namespace flb

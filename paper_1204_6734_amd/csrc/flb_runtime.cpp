@@ -161,6 +161,8 @@ void fill_slot(const flb_params* p, SlotDesc* d) {
   d->ux0 = p->ux0;
   d->uy0 = p->uy0;
   d->rho0f = (float)p->rho0;
+  d->ux0f = (float)p->ux0;
+  d->uy0f = (float)p->uy0;
   for (int a = 0; a < 6; ++a) {
     const double tau = p->tau[a];
     d->rt[a] = 1.0 / tau;
@@ -168,7 +170,16 @@ void fill_slot(const flb_params* p, SlotDesc* d) {
     d->rtf[a] = (float)d->rt[a];
     d->xcf[a] = (float)d->xc[a];
   }
-  for (int i = 0; i < 9; ++i) d->e[i] = equilibrium(i, p->rho0, p->ux0, p->uy0) - kW[i] * p->rho0;
+  for (int i = 0; i < 9; ++i) {
+    d->shift[i] = equilibrium(i, p->rho0, p->ux0, p->uy0);
+    d->shiftf[i] = (float)d->shift[i];
+  }
+}
+
+Shift9 slot_shift(const SlotDesc& d) {
+  Shift9 s;
+  for (int i = 0; i < 9; ++i) s.v[i] = d.shift[i];
+  return s;
 }
 
 // ------------------------------------------------------------ statistics

@@ -22,6 +22,7 @@ int hip_fail(hipError_t e, const char* what);
 int check_params(const flb_params* p);
 int compute_precision(const flb_params* p);
 void fill_slot(const flb_params* p, SlotDesc* d);
+Shift9 slot_shift(const SlotDesc& d);
 void hermite_rows(double m[81]);
 double equilibrium(int i, double rho, double ux, double uy);
 bool fnorm_rows(double ux, double uy, double mt[81]);
@@ -40,23 +41,24 @@ int finish_covariance(const Stats& S, const std::vector<double>& rec, const doub
                       uint64_t sites, const double mt0[81], flb_cov* out);
 
 // launchers (flb_kernels.hip)
-hipError_t launch_step(int storage, int compute, int basis, bool sample, const SlotDesc* d_slots,
-                       const int* d_prefix, int nslots, int total_tiles,
-                       const uint64_t* d_clock, uint32_t step_idx, hipStream_t st);
+hipError_t launch_step(int storage, int compute, int basis, bool sample, int odd,
+                       const SlotDesc* d_slots, const int* d_prefix, int nslots,
+                       int total_tiles, const uint64_t* d_clock, uint32_t step_idx,
+                       hipStream_t st);
 hipError_t launch_tick(uint64_t* d_clock, uint64_t n, hipStream_t st);
 hipError_t launch_write_state(int storage, void* pop, const double* f, int nx, int ny, int odd,
-                              double rho0, int y0, int rows, hipStream_t st);
+                              const Shift9& sh, int y0, int rows, hipStream_t st);
 hipError_t launch_read_state(int storage, const void* pop, double* f, int nx, int ny, int odd,
-                             double rho0, int y0, int rows, hipStream_t st);
+                             const Shift9& sh, int y0, int rows, hipStream_t st);
 hipError_t launch_raw_state(int storage, void* pop, void* buf, int nx, int ny, int odd,
                             int to_buf, int y0, int rows, hipStream_t st);
 hipError_t launch_init(int storage, void* pop, const double* rho, const double* ux,
-                       const double* uy, double rho0, double ux0, double uy0, int nx, int ny,
-                       double mu, uint32_t k0, uint32_t k1, int odd, int y0, int rows,
-                       hipStream_t st);
+                       const double* uy, double rho0, double ux0, double uy0, const Shift9& sh,
+                       int nx, int ny, double mu, uint32_t k0, uint32_t k1, int odd, int y0,
+                       int rows, hipStream_t st);
 hipError_t launch_moments(int storage, const void* pop, const double* B, double* out, int nx,
-                          int ny, int odd, double rho0, int* err, int y0, int rows,
-                          hipStream_t st);
+                          int ny, int odd, double rho0, double ux0, double uy0,
+                          const Shift9& sh, int* err, int y0, int rows, hipStream_t st);
 hipError_t launch_fourier_mode(int storage, const void* pop, double2* partial, int nblocks,
                                int nx, int ny, int odd, int which, int kx, int ky, double rho0,
                                double ux0, double uy0, hipStream_t st);

@@ -192,8 +192,8 @@ int flb_server::admit_locked() {
     // state: equilibrium (or thermal) start, cleared sums and flags
     const double mu = a.p.init == FLB_INIT_THERMAL ? 3.0 * a.p.kT : 0.0;
     HIPC(launch_init(cfg.precision == 0 ? 0 : 1, a.desc.pop, nullptr, nullptr, nullptr, a.p.rho0,
-                     a.p.ux0, a.p.uy0, a.p.nx, a.p.ny, mu, a.desc.k0, a.desc.k1, 0, 0, a.p.ny,
-                     st));
+                     a.p.ux0, a.p.uy0, slot_shift(a.desc), a.p.nx, a.p.ny, mu, a.desc.k0,
+                     a.desc.k1, 0, 0, a.p.ny, st));
     if (a.desc.partials) {
       HIPC(launch_fill(a.desc.partials, (size_t)a.desc.ntiles * kNStat, 0.0, st));
       HIPC(launch_fill(records, (size_t)kServerBlocks * kNStat, 0.0, st));
@@ -289,7 +289,8 @@ int flb_server::run_chunk() {
   for (int k = 0; k < K; ++k) {
     for (int c = 0; c < 2; ++c) {
       if (members[c].empty()) continue;
-      HIPC(launch_step(storage, c, cfg.basis, any_sample, d_slots[c], d_prefix[c],
+      // chunk_steps is even, so every request's own time has the parity of k
+      HIPC(launch_step(storage, c, cfg.basis, any_sample, k & 1, d_slots[c], d_prefix[c],
                        (int)members[c].size(), tiles[c], d_clock, (uint32_t)k, st));
     }
     for (auto& a : active) {
@@ -342,6 +343,7 @@ int flb_server_create(const flb_server_config* cfg, void* hip_stream, flb_server
   flb_server* S = new (std::nothrow) flb_server();
   if (!S) return set_error(FLB_E_OOM, "host allocation");
   S->cfg = *cfg;
+  S->cfg.chunk_steps += S->cfg.chunk_steps & 1;  // even: all requests share the streaming phase
   S->t_start = std::chrono::steady_clock::now();
   auto fail = [&](int rc) {
     flb_server_destroy(S);
