@@ -109,6 +109,8 @@ __device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint32_
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 
 // Per-lattice constants of the collision, in the compute type.  The stored
@@ -348,7 +350,7 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_
   R sr = R(0);
   if (C.noise) {
     site_gaussians<R>(C.k0, C.k1, site, t, 0u, N);
-    sr = sqrt(rho);
+    sr = sqrt_t(rho);
   }
 
   if (BASIS == kBasisHermite) {

@@ -99,3 +99,37 @@ def test_threaded_server_completes_everything(flb):
     assert all(r["t_submit"] <= r["t_admit"] <= r["t_done"] for r in res)
     st = S.stats()
     assert st["completed"] == 10 and st["queued"] == 0
+
+
+def test_ensemble_replica_matches_oracle(flb):
+    """An FP64 ensemble of ragged lattices (tile count not a multiple of the
+    eight XCDs) against the oracle, replica by replica."""
+    import oracle as O
+    taus = I.mixed_taus(2)
+    ps, os_ = [], []
+    for k, ux in enumerate([0.0, 0.12, 0.2]):
+        kw = dict(ux0=ux, kT=1e-4, tau=taus, seed=30 + k)
+        ps.append(flb.make_params(37, 11, precision=flb.FP64, **kw))
+        os_.append(O.Lattice(O.make_params(37, 11, **kw)))
+    E = flb.Ensemble(ps, graph_chunk=4)
+    E.step(23)
+    for k, o in enumerate(os_):
+        o.step(23)
+        f = o.populations()
+        assert np.abs(E.populations(k) - f).max() <= 1e-12 * np.abs(f).max()
+
+
+def test_server_request_matches_oracle(flb):
+    import oracle as O
+    kw = dict(ux0=0.1, kT=1e-4, seed=77, sample_every=1, block_steps=10)
+    p = flb.make_params(29, 13, precision=flb.FP64, **kw)
+    S = flb.Server(64 << 20, max_slots=4, chunk_steps=6, precision=flb.FP64, threaded=False)
+    S.submit(p, 40, tag=1)
+    S.submit(flb.make_params(50, 50, precision=flb.FP64, kT=1e-4, seed=3, sample_every=1), 17)
+    S.drain()
+    r = [x for x in S.poll(8) if x["tag"] == 1][0]
+    o = O.Lattice(O.make_params(29, 13, **kw))
+    o.step(40)
+    co = o.covariance()
+    assert r["cov"]["nsamples"] == co["nsamples"]
+    assert np.abs(r["cov"]["cov_f"] - co["cov_f"]).max() <= 1e-10 * np.abs(co["cov_f"]).max()
