@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the fused fluctuating D2Q9 step (f-norm basis) on one GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|ensemble|serve|fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|ensemble|serve]
 
 Default workload ("large"): one 8192 x 8192 periodic lattice, FP32 storage
 shifted by w_i rho0, rho0 = 1, u_x0 = 0.1, kT = 1e-4, all tau = 1, initial
@@ -13,8 +13,11 @@ shear-mode amplitude j~_y(k = 2 pi / L) is read back.
 Prints one JSON line: MLUPS (lattice-site updates per second / 1e6) over
 the timed steps, the step kernel's achieved HBM bandwidth against the
 8 TB/s peak (72 algorithmic bytes per site update: nine FP32 reads and nine
-FP32 writes in place), and the FP64 CPU oracle's rate on a bounded sample
-of the same workload.
+FP32 writes in place), a served-requests measurement (solves/s and p50/p99
+latency of mixed Poisson-arriving requests through the continuous-batching
+server, next to the plain FP64 one-lattice-per-launch path on the same
+arrivals), and the FP64 CPU oracle's rate on a bounded sample of the
+large workload.
 """
 from __future__ import annotations
 
@@ -117,6 +120,87 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
             "dtype": "f32", "kernel_name": "step_fp32_8192"}
 
 
+def run_ensemble(F, torch, steps: int, warmup: int, n: int = 64, side: int = 128,
+                 chunk: int = 100, every: int = 10):
+    """64 replicas of 128 x 128 in one batched launch per step, replayed from
+    a captured hipGraph of `chunk` steps; correlators every `every` steps."""
+    from paper_1204_6734_amd import inputs as I
+    ps = [F.make_params(side, side, precision=F.FP32_SHIFTED, ux0=m["ux0"], kT=m["kT"],
+                        seed=m["seed"], sample_every=every, block_steps=100)
+          for m in I.ensemble_members(n, seed=3)]
+    E = F.Ensemble(ps, stream=torch.cuda.current_stream(), graph_chunk=chunk)
+    E.step(warmup)
+    E.sync()
+    t0 = time.perf_counter()
+    E.step(steps)
+    E.sync()
+    dt = time.perf_counter() - t0
+    c = E.covariance(0)
+    return {"mlups": n * side * side * steps / dt / 1e6, "seconds": dt, "replicas": n,
+            "side": side, "steps": steps, "graph_chunk": chunk, "sample_every": every,
+            "replica0_nsamples": c["nsamples"]}
+
+
+def run_serving(F, torch, nreq: int = 40, rate: float = 50.0, chunk: int = 100,
+                every: int = 10, baseline: bool = True):
+    """Poisson arrivals of mixed requests (side log-uniform 64..2048, steps
+    log-uniform 1e3..1e5, kT log-uniform 1e-5..1e-3, u_x0 ~ U[0, 0.2], FP32
+    shifted, correlators every `every` steps) into the continuous-batching
+    server, then the same arrivals through the plain FP64 path (one lattice
+    per launch, first come first served)."""
+    from paper_1204_6734_amd import inputs as I
+    reqs = I.serving_requests(nreq, rate=rate, seed=4)
+
+    def params(r, precision):
+        return F.make_params(r["side"], r["side"], precision=precision, ux0=r["ux0"], kT=r["kT"],
+                             seed=r["seed"], sample_every=every, block_steps=50)
+
+    def summarize(lat, t_first, t_last, work):
+        lat = sorted(lat)
+        q = lambda f: lat[min(len(lat) - 1, int(f * len(lat)))]
+        span = t_last - t_first
+        return {"solves_per_s": len(lat) / span, "p50_latency_s": q(0.5), "p99_latency_s": q(0.99),
+                "makespan_s": span, "site_updates_per_s": work / span}
+
+    work = sum(r["side"] ** 2 * r["nsteps"] for r in reqs)
+    budget = 64 << 30
+    S = F.Server(budget, max_slots=64, chunk_steps=chunk, precision=F.FP32_SHIFTED,
+                 threaded=True)
+    t0 = time.perf_counter()
+    for k, r in enumerate(reqs):
+        while time.perf_counter() - t0 < r["t"]:
+            time.sleep(0.0005)
+        S.submit(params(r, F.FP32_SHIFTED), r["nsteps"], tag=k)
+    S.drain()
+    res = S.poll(nreq + 8)
+    st = S.stats()
+    S.close()
+    assert len(res) == nreq and all(x["status"] == 0 for x in res)
+    # the server clock starts at creation (t0 up to a few microseconds)
+    lat = [x["t_done"] - x["t_submit"] for x in res]
+    out = {"requests": nreq, "rate_per_s": rate, "chunk_steps": chunk, "sample_every": every,
+           "served": summarize(lat, min(x["t_submit"] for x in res),
+                               max(x["t_done"] for x in res), work),
+           "device_busy_fraction": st["busy_s"] / max(st["wall_s"], 1e-9)}
+    if baseline:
+        lat0 = []
+        t0 = time.perf_counter()
+        tfirst = None
+        for k, r in enumerate(reqs):
+            while time.perf_counter() - t0 < r["t"]:
+                time.sleep(0.0005)
+            if tfirst is None:
+                tfirst = time.perf_counter() - t0
+            L = F.Lattice(params(r, F.FP64), stream=torch.cuda.current_stream())
+            L.step(r["nsteps"])
+            L.covariance()
+            L.close()
+            lat0.append(time.perf_counter() - t0 - r["t"])
+        out["baseline_fp64_one_per_launch"] = summarize(lat0, tfirst, time.perf_counter() - t0,
+                                                        work)
+    return out
+
+
 def copy_calibration(reps: int = 5):
     """A plain copy kernel of known size: each launch reads and writes
     exactly 1 GiB.  Its FETCH_SIZE / WRITE_SIZE readings scale the step
@@ -136,7 +220,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="large", choices=["large"])
+    ap.add_argument("--workload", default="large", choices=["large", "ensemble", "serve"])
+    ap.add_argument("--requests", type=int, default=None,
+                    help="serving window (default 40 in the main line, 400 with --workload serve)")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -156,6 +243,14 @@ def main():
     F.load()
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.workload == "ensemble":
+        r = run_ensemble(F, torch, args.steps, args.warmup)
+        print(json.dumps({"workload": "64 x 128^2 FP32 ensemble, hipGraph", **r}), flush=True)
+        return
+    if args.workload == "serve":
+        r = run_serving(F, torch, nreq=args.requests or 400)
+        print(json.dumps({"workload": "serving, Poisson 50/s", **r}), flush=True)
+        return
     r = run_large(F, torch, args.steps, args.warmup, nx=args.nx)
     mlups = r["sites"] * args.steps / r["dt"] / 1e6
     bps = BYTES_PER_SITE[r["dtype"]]
@@ -174,6 +269,8 @@ def main():
                      "launches": r["launches"]},
         "pct_hbm_roofline": round(100 * mlups * 1e6 * bps / (HBM_PEAK_GBS * 1e9), 2),
     }
+    if not args.no_serving:
+        out["serving"] = run_serving(F, torch, nreq=args.requests or 40)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -98,8 +98,12 @@ typedef struct {
 
 typedef struct flb_lattice flb_lattice;
 
-/* Creates a lattice, allocates its device memory and initialises the
- * populations per p->init.  hip_stream: hipStream_t or NULL. */
+/* Creates a periodic lattice (Sec. III set-up) and initialises the
+ * populations per p->init: f^0(rho0, u0) of eq. (A1), optionally plus
+ * ideal-gas fluctuations with the covariance of eq. (16) scaled by mu.
+ * hip_stream: a hipStream_t or NULL.  *out receives a library-owned handle.
+ * Errors: FLB_E_ARG (sizes, tau, kT), FLB_E_INVALID_VELOCITY (u0 outside the
+ * region of Fig. 11), FLB_E_OOM, FLB_E_HIP; *out is NULL then. */
 int flb_lattice_create(const flb_params* p, void* hip_stream, flb_lattice** out);
 
 /* Device bytes a lattice with these parameters needs (for create_on). */
@@ -111,13 +115,20 @@ size_t flb_lattice_bytes(const flb_params* p);
 int flb_lattice_create_on(const flb_params* p, void* dev_buf, size_t bytes, void* hip_stream,
                           flb_lattice** out);
 
-/* f = f^0(rho(x), u(x)) per site (eq. (A1)); host arrays [ny][nx]. */
+/* f = f^0(rho(x), u(x)) per site (eq. (A1)); three host arrays [ny][nx]
+ * (read only, caller-owned).  Synchronous.  FLB_E_ARG on NULL. */
 int flb_lattice_set_fields(flb_lattice* L, const double* rho, const double* ux, const double* uy);
 
-/* Replace the populations (host [9][ny][nx], unshifted) and set the time. */
+/* Replace the populations (host [9][ny][nx], unshifted FP64, caller-owned)
+ * and set the lattice time t (the noise of step t is keyed by t). */
 int flb_lattice_set_populations(flb_lattice* L, const double* f, uint64_t t);
 
-/* Enqueue nsteps updates (collision, stream, sampling when due). */
+/* Enqueue nsteps updates of eq. (1): collision in the basis p->basis (eq.
+ * (6) with the f-norm of eqs. (27)-(32), the Hermite norm of App. A or the
+ * grid-velocity basis of Sec. IV), FDT noise of eq. (20), streaming; and,
+ * when due, correlator samples (eqs. (16), (23)) and structure-factor
+ * samples (eqs. (24)-(26)) of the pre-collision state.  Asynchronous on the
+ * handle's stream; device errors surface at the next sync/read. */
 int flb_lattice_step(flb_lattice* L, uint64_t nsteps);
 
 /* Wait for the stream; returns the first device error (FLB_E_INVALID_VELOCITY
@@ -125,9 +136,17 @@ int flb_lattice_step(flb_lattice* L, uint64_t nsteps);
  * naming the step. */
 int flb_lattice_sync(flb_lattice* L);
 
+/* Current populations, unshifted FP64, into caller-owned host [9][ny][nx].
+ * Synchronises; returns a pending device error instead of data. */
 int flb_lattice_read_populations(flb_lattice* L, double* f);
-/* Moments per site in basis `at` (flb_moment_basis); host [9][ny][nx]. */
+/* Moments per site into host [9][ny][nx]: FLB_AT_LOCAL = f-norm at the local
+ * velocity (eq. (31): rho, 0, 0, then the non-equilibrium M~^{3..8}),
+ * FLB_AT_U0 = f-norm at (rho0, u0) (the measurement basis of Sec. IV, after
+ * eq. (34)), FLB_AT_HERMITE = rows of eq. (A3).  Synchronises. */
 int flb_lattice_read_moments(flb_lattice* L, int32_t at, double* m);
+/* Correlators of all samples since creation / reset_stats (eqs. (16), (23));
+ * standard errors from time blocks of p->block_steps samples (pairs of
+ * blocks merge when 1024 are full).  Synchronises. */
 int flb_lattice_read_covariance(flb_lattice* L, flb_cov* out);
 /* <|dA(k)|^2> / (nx ny) (which = RHO, JX, JY) or <dj~_x(k) dj~_y(-k)> / (nx ny)
  * (real, imaginary part), k = 2 pi (kx/nx, ky/ny), host [ky][kx]. */
@@ -135,6 +154,8 @@ int flb_lattice_read_structure_factor(flb_lattice* L, int32_t which, double* out
 /* sum_x dA(x) exp(-i k.x) of the current state, which = 0 rho, 1 j~_x, 2 j~_y. */
 int flb_lattice_read_fourier_mode(flb_lattice* L, int32_t which, int32_t kx, int32_t ky,
                                   double out[2]);
+/* Clears correlator and structure-factor accumulators (e.g. after
+ * thermalisation).  Synchronises. */
 int flb_lattice_reset_stats(flb_lattice* L);
 
 /* Checkpoint: exact storage bits plus time and parameters; restoring into a
@@ -144,8 +165,10 @@ size_t flb_lattice_checkpoint_bytes(flb_lattice* L);
 int flb_lattice_checkpoint(flb_lattice* L, void* host, size_t bytes);
 int flb_lattice_restore(flb_lattice* L, const void* host, size_t bytes);
 
+/* Lattice time (steps taken; the streaming phase is its parity). */
 uint64_t flb_lattice_time(flb_lattice* L);
-int64_t flb_lattice_error_step(flb_lattice* L); /* -1 when no error */
+/* Step at which the first device error was raised, -1 when none. */
+int64_t flb_lattice_error_step(flb_lattice* L);
 
 /* Device time of the step kernels enqueued since the last reset, measured
  * with HIP events around each launch (enable first; adds two events per
@@ -153,7 +176,9 @@ int64_t flb_lattice_error_step(flb_lattice* L); /* -1 when no error */
 int flb_lattice_profile(flb_lattice* L, int32_t on);
 int flb_lattice_kernel_time(flb_lattice* L, double* ms, uint64_t* launches);
 
+/* Releases the handle and the device memory it owns (NULL is ignored). */
 void flb_lattice_destroy(flb_lattice* L);
+/* Message of the last failed call on this thread (never NULL). */
 const char* flb_last_error(void);
 
 /* ------------------------------------------------------------- ensembles

@@ -241,30 +241,40 @@ int Group::launch_one(uint32_t k, bool sample, int odd) {
 // Whether every slot samples at every step or never (then the step schedule
 // inside a chunk does not depend on the time and a captured graph can be
 // replayed), and no structure factors are taken.
+// A captured chunk of graph_chunk steps can be replayed at every time that
+// is a multiple of graph_chunk when each slot's sampling interval divides the
+// chunk (the sampling pattern inside a chunk is then the same every time)
+// and no structure factors are taken.
 bool Group::graph_friendly() const {
-  if (d_skacc) return false;
+  if (d_skacc || graph_chunk <= 0) return false;
   for (auto& p : P)
-    if (p.sample_every > 1) return false;
+    if (p.sample_every > 0 && graph_chunk % p.sample_every != 0) return false;
   return true;
 }
 
-// Steps until the next time-block close of any slot (replays must not
-// straddle one).
+// Steps from time t until (and including) the step whose sample closes a
+// time block of some slot; replays must not straddle such a step.
 uint64_t Group::steps_to_close() const {
   uint64_t m = ~0ull;
-  for (int s = 0; s < (int)P.size(); ++s)
-    if (P[s].sample_every == 1 && stats[s].tb_len > 0)
-      m = std::min(m, stats[s].tb_len - stats[s].tb_fill);
+  for (int s = 0; s < (int)P.size(); ++s) {
+    const uint64_t se = (uint64_t)P[s].sample_every;
+    if (se == 0 || stats[s].tb_len == 0) continue;
+    const uint64_t left = stats[s].tb_len - stats[s].tb_fill;  // samples to the close
+    const uint64_t first = (t + se - 1) / se * se;              // next sampled time
+    m = std::min(m, first + (left - 1) * se - t + 1);
+  }
   return m;
 }
 
 int Group::capture_graph() {
   if (graph_exec) return FLB_OK;
-  bool sample = false;
-  for (auto& p : P) sample |= p.sample_every == 1;
   HIPC(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   for (int k = 0; k < graph_chunk; ++k) {
-    // replays start at even times (see step()), so step k has parity k & 1
+    // replays start at multiples of graph_chunk (even), so step k of a chunk
+    // has parity k & 1 and a slot samples there iff k is a multiple of its
+    // interval
+    bool sample = false;
+    for (auto& p : P) sample |= p.sample_every > 0 && k % p.sample_every == 0;
     hipError_t e = launch_step(storage, compute, basis, sample, k & 1, d_slots, d_prefix,
                                (int)P.size(), total_tiles, d_clock, (uint32_t)k, st);
     if (e != hipSuccess) {
@@ -282,11 +292,12 @@ int Group::capture_graph() {
 
 int Group::step(uint64_t nsteps) {
   const int n = (int)P.size();
+  const uint64_t K = (uint64_t)graph_chunk;
+  const bool use_graph = graph_friendly();
   uint64_t done = 0;
   while (done < nsteps) {
     const uint64_t left = nsteps - done;
-    if (graph_chunk > 0 && graph_friendly() && left >= (uint64_t)graph_chunk &&
-        (t & 1) == 0 && steps_to_close() >= (uint64_t)graph_chunk) {
+    if (use_graph && left >= K && t % K == 0 && steps_to_close() >= K) {
       int rc = capture_graph();
       if (rc != FLB_OK) return rc;
       if (profiling) {
@@ -297,24 +308,25 @@ int Group::step(uint64_t nsteps) {
         HIPC(hipGraphLaunch(graph_exec, st));
         HIPC(hipEventRecord(ev.second, st));
         events.push_back(ev);
-        prof_launches += (uint64_t)graph_chunk;
+        prof_launches += K;
       } else {
         HIPC(hipGraphLaunch(graph_exec, st));
       }
-      for (int k = 0; k < graph_chunk; ++k) {
+      for (uint64_t k = 0; k < K; ++k) {
         rc = after_step(t + k);
         if (rc != FLB_OK) return rc;
       }
-      t += (uint64_t)graph_chunk;
-      done += (uint64_t)graph_chunk;
+      t += K;
+      done += K;
       continue;
     }
-    // eager chunk: up to 2^30 steps, or up to the next time-block close when
-    // a graph could resume after it
+    // eager chunk: up to 2^30 steps; with graphs, only up to the next
+    // multiple of the chunk length or the next time-block close, after which
+    // replays can resume
     uint64_t chunk = std::min<uint64_t>(left, 1ull << 30);
-    if (graph_chunk > 0 && graph_friendly()) {
-      chunk = std::min(chunk, std::max<uint64_t>(1, steps_to_close()));
-      if (t & 1) chunk = 1;  // realign replays to even times
+    if (use_graph) {
+      const uint64_t to_align = t % K == 0 ? K : K - t % K;
+      chunk = std::min(chunk, std::min(to_align, std::max<uint64_t>(1, steps_to_close())));
     }
     for (uint64_t k = 0; k < chunk; ++k) {
       const uint64_t tt = t + k;

@@ -269,13 +269,11 @@ int flb_server::run_chunk() {
     h_slots[c].clear();
     h_prefix[c].assign(1, 0);
   }
-  bool any_sample = false;
   for (int i = 0; i < (int)active.size(); ++i) {
     const int c = active[i].cls;
     members[c].push_back(i);
     h_slots[c].push_back(active[i].desc);
     h_prefix[c].push_back(h_prefix[c].back() + active[i].desc.ntiles);
-    any_sample |= active[i].p.sample_every > 0;
   }
   for (int c = 0; c < 2; ++c) {
     tiles[c] = h_prefix[c].back();
@@ -287,8 +285,15 @@ int flb_server::run_chunk() {
   }
   const int storage = cfg.precision == 0 ? 0 : 1;
   for (int k = 0; k < K; ++k) {
+    // the sampling variant only where some request of the class samples
+    bool due[2] = {false, false};
+    for (auto& a : active) {
+      const uint64_t own = a.desc.t0 + clock + (uint64_t)k;
+      due[a.cls] |= own < a.nsteps && a.p.sample_every > 0 && own % (uint64_t)a.p.sample_every == 0;
+    }
     for (int c = 0; c < 2; ++c) {
       if (members[c].empty()) continue;
+      const bool any_sample = due[c];
       // chunk_steps is even, so every request's own time has the parity of k
       HIPC(launch_step(storage, c, cfg.basis, any_sample, k & 1, d_slots[c], d_prefix[c],
                        (int)members[c].size(), tiles[c], d_clock, (uint32_t)k, st));

@@ -133,3 +133,33 @@ def test_server_request_matches_oracle(flb):
     co = o.covariance()
     assert r["cov"]["nsamples"] == co["nsamples"]
     assert np.abs(r["cov"]["cov_f"] - co["cov_f"]).max() <= 1e-10 * np.abs(co["cov_f"]).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sampling_variant_does_not_change_the_trajectory(flb, prec):
+    """The sampling kernel variant and the plain one update identically, so a
+    request's populations do not depend on whether others sample."""
+    precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+    kw = dict(precision=precision, ux0=0.1, kT=1e-4, tau=I.mixed_taus(2), seed=12)
+    a = flb.Lattice(flb.make_params(66, 18, sample_every=1, **kw))
+    b = flb.Lattice(flb.make_params(66, 18, sample_every=0, **kw))
+    a.step(31)
+    b.step(31)
+    np.testing.assert_array_equal(a.populations(), b.populations())
+
+
+def test_ensemble_graph_with_sampling_interval(flb):
+    """Replays with a sampling interval > 1 and time blocks that do not line up
+    with the replay chunk equal the eager single-lattice runs."""
+    ps = members(flb, 3, 64, 24, flb.FP32_SHIFTED, sample_every=5, block_steps=7)
+    E = flb.Ensemble(ps, graph_chunk=10)
+    E.step(3)      # misalign first
+    E.step(120)
+    for i in range(3):
+        L = flb.Lattice(ps[i])
+        L.step(123)
+        np.testing.assert_array_equal(E.populations(i), L.populations())
+        ce, cl = E.covariance(i), L.covariance()
+        assert ce["nsamples"] == cl["nsamples"] == 25 * 64 * 24
+        assert ce["nblocks"] == cl["nblocks"] == 3
+        np.testing.assert_array_equal(ce["cov_f"], cl["cov_f"])
