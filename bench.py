@@ -86,6 +86,7 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                       init=F.INIT_FIELDS, sk_every=every)
     L = F.Lattice(p, stream=stream)
     L.set_fields(*I.shear_wave_fields(nx, nx, ux0=0.1, amp=1e-3))
+    tune = L.autotune(reps=3)  # trial steps run on a copy of the state
 
     def run(n):
         done = 0
@@ -112,6 +113,7 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
     sites = nx * nx
     return {"sites": sites, "dt": dt, "kernel_ms": kms / max(launches, 1), "launches": launches,
             "mode_log": [abs(z) for z in log[-3:]],
+            "launch": {"chosen": L.get_launch(), "candidates": tune},
             "config": {"workload": f"{nx}x{nx} D2Q9 FP32-shifted, rho0=1, u_x0=0.1, kT=1e-4, "
                                    f"tau=1, shear wave 1e-3 sin(2 pi x/L); S(k) and "
                                    f"j~_y(2 pi/L) every {every} steps",
@@ -129,6 +131,7 @@ def run_ensemble(F, torch, steps: int, warmup: int, n: int = 64, side: int = 128
                         seed=m["seed"], sample_every=every, block_steps=100)
           for m in I.ensemble_members(n, seed=3)]
     E = F.Ensemble(ps, stream=torch.cuda.current_stream(), graph_chunk=chunk)
+    tune = E.autotune(reps=5)
     E.step(warmup)
     E.sync()
     t0 = time.perf_counter()
@@ -138,7 +141,8 @@ def run_ensemble(F, torch, steps: int, warmup: int, n: int = 64, side: int = 128
     c = E.covariance(0)
     return {"mlups": n * side * side * steps / dt / 1e6, "seconds": dt, "replicas": n,
             "side": side, "steps": steps, "graph_chunk": chunk, "sample_every": every,
-            "replica0_nsamples": c["nsamples"]}
+            "replica0_nsamples": c["nsamples"],
+            "launch": {"chosen": E.get_launch(), "candidates": tune}}
 
 
 def run_serving(F, torch, nreq: int = 40, rate: float = 50.0, chunk: int = 100,
@@ -171,7 +175,9 @@ def run_serving(F, torch, nreq: int = 40, rate: float = 50.0, chunk: int = 100,
         while time.perf_counter() - t0 < r["t"]:
             time.sleep(0.0005)
         S.submit(params(r, F.FP32_SHIFTED), r["nsteps"], tag=k)
+    print(f"serving: {nreq} requests submitted", file=sys.stderr, flush=True)
     S.drain()
+    print("serving: drained", file=sys.stderr, flush=True)
     res = S.poll(nreq + 8)
     st = S.stats()
     S.close()
@@ -196,6 +202,8 @@ def run_serving(F, torch, nreq: int = 40, rate: float = 50.0, chunk: int = 100,
             L.covariance()
             L.close()
             lat0.append(time.perf_counter() - t0 - r["t"])
+            if (k + 1) % 10 == 0:
+                print(f"baseline: {k + 1}/{nreq} done", file=sys.stderr, flush=True)
         out["baseline_fp64_one_per_launch"] = summarize(lat0, tfirst, time.perf_counter() - t0,
                                                         work)
     return out
@@ -268,6 +276,7 @@ def main():
                      "bytes_per_site": bps, "kernel_ms": round(r["kernel_ms"], 4),
                      "launches": r["launches"]},
         "pct_hbm_roofline": round(100 * mlups * 1e6 * bps / (HBM_PEAK_GBS * 1e9), 2),
+        "launch": r["launch"],
     }
     if not args.no_serving:
         out["serving"] = run_serving(F, torch, nreq=args.requests or 40)

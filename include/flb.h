@@ -201,6 +201,51 @@ int flb_ensemble_profile(flb_ensemble* E, int32_t on);
 int flb_ensemble_kernel_time(flb_ensemble* E, double* ms, uint64_t* launches);
 void flb_ensemble_destroy(flb_ensemble* E);
 
+/* ------------------------------------------------------------ launch shape
+ * The batched step works on 64 x 4 tiles of sites (one 64-lane wavefront per
+ * tile row).  Its launch shape is a tuning choice that never changes a
+ * result: every shape computes bit-identical populations and correlator
+ * sums (each tile forms its partial sums in the same order).
+ *   tiles_per_block  tiles per workgroup: 1, 2 or 4 (256, 512, 1024 threads)
+ *   grid_blocks      0: one workgroup per group of tiles; > 0 (a multiple
+ *                    of 8, the XCD count): a persistent grid of that many
+ *                    workgroups, each striding over the tile groups
+ *   ms_per_step      output of the autotuner: measured device time per step
+ *                    (one even and one odd step averaged); ignored on input
+ * Steps that sample correlators or structure-factor fields always give each
+ * tile group its own workgroup, and they and every step computed in FP64
+ * take at most 2 tiles per workgroup (a larger value is lowered to 2).
+ * A new lattice or ensemble starts with {1, 0}, or with the shape an earlier
+ * autotune in this process chose for the same device, precision, basis and
+ * tile count. */
+typedef struct {
+  int32_t tiles_per_block;
+  int32_t grid_blocks;
+  double ms_per_step;
+} flb_launch_config;
+
+/* Time every candidate shape for `reps` (1..1000) pairs of steps, keep the
+ * fastest for all later steps (and for new lattices of the same kind in this
+ * process) and write up to `max_results` measurements, fastest first, to
+ * `results` (may be NULL when max_results is 0); *n_results (nullable)
+ * receives the number of candidates measured.  Timing follows a device
+ * warm-up of at least 50 ms and takes each shape's faster of two interleaved
+ * rounds.  The trial steps run on a device copy of the populations, which is
+ * put back afterwards: the lattice's state, time, statistics and error flags
+ * are as before the call.  Synchronises the stream; allocates a temporary
+ * device buffer the size of the populations (FLB_E_OOM if that fails).  A
+ * captured step graph is dropped and recaptured with the new shape. */
+int flb_lattice_autotune(flb_lattice* L, int32_t reps, flb_launch_config* results,
+                         int32_t max_results, int32_t* n_results);
+int flb_ensemble_autotune(flb_ensemble* E, int32_t reps, flb_launch_config* results,
+                          int32_t max_results, int32_t* n_results);
+/* Force a shape (FLB_E_ARG for tiles_per_block not in {1, 2, 4} or a
+ * negative grid_blocks or one that is not a multiple of 8). */
+int flb_lattice_set_launch(flb_lattice* L, const flb_launch_config* c);
+int flb_ensemble_set_launch(flb_ensemble* E, const flb_launch_config* c);
+int flb_lattice_get_launch(flb_lattice* L, flb_launch_config* c);
+int flb_ensemble_get_launch(flb_ensemble* E, flb_launch_config* c);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of simulation requests of mixed size, temperature and
  * background velocity.  Requests wait in FIFO order; one is admitted as soon

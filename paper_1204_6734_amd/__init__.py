@@ -68,6 +68,11 @@ class Result(C.Structure):
     ]
 
 
+class LaunchConfig(C.Structure):
+    _fields_ = [("tiles_per_block", C.c_int32), ("grid_blocks", C.c_int32),
+                ("ms_per_step", C.c_double)]
+
+
 class FlbError(RuntimeError):
     def __init__(self, code: int, what: str, msg: str):
         super().__init__(f"{what} failed ({code}): {msg}")
@@ -103,6 +108,14 @@ _SIGS = {
     "flb_ensemble_read_covariance": [C.c_void_p, C.c_int32, C.POINTER(Cov)],
     "flb_ensemble_profile": [C.c_void_p, C.c_int32],
     "flb_ensemble_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
+    "flb_lattice_autotune": [C.c_void_p, C.c_int32, C.POINTER(LaunchConfig), C.c_int32,
+                             C.POINTER(C.c_int32)],
+    "flb_ensemble_autotune": [C.c_void_p, C.c_int32, C.POINTER(LaunchConfig), C.c_int32,
+                              C.POINTER(C.c_int32)],
+    "flb_lattice_set_launch": [C.c_void_p, C.POINTER(LaunchConfig)],
+    "flb_ensemble_set_launch": [C.c_void_p, C.POINTER(LaunchConfig)],
+    "flb_lattice_get_launch": [C.c_void_p, C.POINTER(LaunchConfig)],
+    "flb_ensemble_get_launch": [C.c_void_p, C.POINTER(LaunchConfig)],
     "flb_server_create": [C.POINTER(ServerConfig), C.c_void_p, C.POINTER(C.c_void_p)],
     "flb_server_submit": [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)],
     "flb_server_pump": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
@@ -194,8 +207,36 @@ def _stream_ptr(stream):
     return int(getattr(stream, "cuda_stream", stream))
 
 
-class Lattice:
+class _Tunable:
+    """Launch-shape control shared by lattices and ensembles (flb_*_autotune,
+    flb_*_set_launch, flb_*_get_launch)."""
+
+    _kind = ""
+
+    def autotune(self, reps: int = 5, max_results: int = 32) -> list:
+        """Time every launch shape on a copy of the state and keep the fastest;
+        returns the measurements, fastest first, as dicts."""
+        out = (LaunchConfig * max_results)()
+        n = C.c_int32()
+        fn = getattr(load(), f"flb_{self._kind}_autotune")
+        _check(fn(self.h, reps, out, max_results, C.byref(n)), "autotune")
+        return [{"tiles_per_block": c.tiles_per_block, "grid_blocks": c.grid_blocks,
+                 "ms_per_step": c.ms_per_step} for c in out[:min(n.value, max_results)]]
+
+    def set_launch(self, tiles_per_block: int = 1, grid_blocks: int = 0):
+        c = LaunchConfig(tiles_per_block, grid_blocks, 0.0)
+        _check(getattr(load(), f"flb_{self._kind}_set_launch")(self.h, C.byref(c)), "set_launch")
+
+    def get_launch(self) -> dict:
+        c = LaunchConfig()
+        _check(getattr(load(), f"flb_{self._kind}_get_launch")(self.h, C.byref(c)), "get_launch")
+        return {"tiles_per_block": c.tiles_per_block, "grid_blocks": c.grid_blocks}
+
+
+class Lattice(_Tunable):
     """One periodic lattice on the GPU (flb_lattice_*)."""
+
+    _kind = "lattice"
 
     def __init__(self, p: Params, stream=None, device_buffer=None):
         lib = load()
@@ -296,8 +337,10 @@ class Lattice:
         return ms.value, n.value
 
 
-class Ensemble:
+class Ensemble(_Tunable):
     """Replicas of one lattice shape in one batched launch (flb_ensemble_*)."""
+
+    _kind = "ensemble"
 
     def __init__(self, params: list, stream=None, graph_chunk: int = 0):
         lib = load()

@@ -342,7 +342,6 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_
                                        uint64_t t) {
   LocalState<R> S;
   if (!local_state(h, C.rho0, C.ux0, C.uy0, S)) return kErrNonFinite;
-  const Moments<R>& m = S.m;
   const R rho = S.rho, ux = S.ux, uy = S.uy;
   const R* d = S.d;
 

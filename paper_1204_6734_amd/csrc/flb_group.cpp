@@ -124,6 +124,8 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
   HIPC(hipGetDevice(&dev_id));
   HIPC(hipGetDeviceProperties(&prop, dev_id));
   max_lds = prop.sharedMemPerBlock;
+  device = dev_id;
+  launch = tuned_launch(*this);
   // per-slot pointers and measurement bases
   mt0.assign(n, std::vector<double>(81));
   stats.assign(n, Stats{});
@@ -227,14 +229,14 @@ int Group::launch_one(uint32_t k, bool sample, int odd) {
     HIPC(hipEventCreate(&ev.second));
     HIPC(hipEventRecord(ev.first, st));
     HIPC(launch_step(storage, compute, basis, sample, odd, d_slots, d_prefix, (int)P.size(),
-                     total_tiles, d_clock, k, st));
+                     total_tiles, d_clock, k, launch, st));
     HIPC(hipEventRecord(ev.second, st));
     events.push_back(ev);
     prof_launches += 1;
     return FLB_OK;
   }
   HIPC(launch_step(storage, compute, basis, sample, odd, d_slots, d_prefix, (int)P.size(),
-                   total_tiles, d_clock, k, st));
+                   total_tiles, d_clock, k, launch, st));
   return FLB_OK;
 }
 
@@ -276,7 +278,7 @@ int Group::capture_graph() {
     bool sample = false;
     for (auto& p : P) sample |= p.sample_every > 0 && k % p.sample_every == 0;
     hipError_t e = launch_step(storage, compute, basis, sample, k & 1, d_slots, d_prefix,
-                               (int)P.size(), total_tiles, d_clock, (uint32_t)k, st);
+                               (int)P.size(), total_tiles, d_clock, (uint32_t)k, launch, st);
     if (e != hipSuccess) {
       hipGraph_t g;
       (void)hipStreamEndCapture(st, &g);
@@ -753,14 +755,7 @@ int flb_ensemble_create(const flb_params* ps, int32_t n, void* hip_stream, flb_e
 int flb_ensemble_set_graph_chunk(flb_ensemble* E, int32_t steps) {
   NEED(E);
   if (steps < 0 || steps > (1 << 16)) return flb::set_error(FLB_E_ARG, "bad chunk %d", steps);
-  if (E->g.graph_exec) {
-    (void)hipGraphExecDestroy(E->g.graph_exec);
-    E->g.graph_exec = nullptr;
-  }
-  if (E->g.graph) {
-    (void)hipGraphDestroy(E->g.graph);
-    E->g.graph = nullptr;
-  }
+  E->g.drop_graph();
   E->g.graph_chunk = steps + (steps & 1);  // even: replays keep the streaming phase
   return FLB_OK;
 }
@@ -793,5 +788,36 @@ int flb_ensemble_kernel_time(flb_ensemble* E, double* ms, uint64_t* launches) {
   return E->g.kernel_time(ms, launches);
 }
 void flb_ensemble_destroy(flb_ensemble* E) { delete E; }
+
+int flb_lattice_autotune(flb_lattice* L, int32_t reps, flb_launch_config* results,
+                         int32_t max_results, int32_t* n_results) {
+  NEED(L);
+  return L->g.autotune(reps, results, max_results, n_results);
+}
+int flb_ensemble_autotune(flb_ensemble* E, int32_t reps, flb_launch_config* results,
+                          int32_t max_results, int32_t* n_results) {
+  NEED(E);
+  return E->g.autotune(reps, results, max_results, n_results);
+}
+int flb_lattice_set_launch(flb_lattice* L, const flb_launch_config* c) {
+  NEED(L);
+  return L->g.set_launch(c);
+}
+int flb_ensemble_set_launch(flb_ensemble* E, const flb_launch_config* c) {
+  NEED(E);
+  return E->g.set_launch(c);
+}
+int flb_lattice_get_launch(flb_lattice* L, flb_launch_config* c) {
+  NEED(L);
+  if (!c) return flb::set_error(FLB_E_ARG, "null output");
+  *c = flb_launch_config{L->g.launch.tiles_per_block, L->g.launch.grid_blocks, 0.0};
+  return FLB_OK;
+}
+int flb_ensemble_get_launch(flb_ensemble* E, flb_launch_config* c) {
+  NEED(E);
+  if (!c) return flb::set_error(FLB_E_ARG, "null output");
+  *c = flb_launch_config{E->g.launch.tiles_per_block, E->g.launch.grid_blocks, 0.0};
+  return FLB_OK;
+}
 
 }  // extern "C"

@@ -49,6 +49,9 @@ struct Group {
   int64_t err_step_host = -1;
   std::vector<Stats> stats;
   std::vector<std::vector<double>> mt0;
+  // launch shape of the step kernel
+  LaunchCfg launch;
+  int device = 0;
   // graphs
   int graph_chunk = 0;
   hipGraph_t graph = nullptr;
@@ -87,6 +90,13 @@ struct Group {
   int checkpoint(void* host, size_t bytes);
   int restore(const void* host, size_t bytes);
   int kernel_time(double* ms, uint64_t* launches);
+  void drop_graph();
+  int set_launch(const flb_launch_config* c);
+  int autotune(int reps, flb_launch_config* results, int max_results, int* n_results);
 };
+
+// Launch shape an earlier autotune in this process chose for groups like g
+// (same device, storage, compute, basis and tile count), else the default.
+LaunchCfg tuned_launch(const Group& g);
 
 }  // namespace flb

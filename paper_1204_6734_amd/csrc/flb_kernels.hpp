@@ -10,6 +10,8 @@ namespace flb {
 constexpr int kTileX = 64;   // one wavefront per tile row: coalesced rows
 constexpr int kTileY = 4;    // four wavefronts per 256-thread block
 constexpr int kBlock = kTileX * kTileY;
+constexpr int kMaxTilesPerBlock = 4;  // workgroups of up to 1024 threads
+constexpr int kMaxBlock = kBlock * kMaxTilesPerBlock;
 constexpr int kNStat = 54;   // 9 first moments + 45 unique second moments
 constexpr int kMaxTimeBlocks = 1024;
 enum : int { kErrInvalidVelocity = 1, kErrNonFinite = 2 };
@@ -40,6 +42,15 @@ struct SlotDesc {
 }  // namespace flb
 
 namespace flb {
+// Launch shape of the batched step: tiles per workgroup (1, 2 or 4) and the
+// grid (0: one workgroup per tile group; > 0, a multiple of 8: a persistent
+// grid of that many workgroups striding over the tile groups).  Every shape
+// computes bit-identical results.
+struct LaunchCfg {
+  int tiles_per_block = 1;
+  int grid_blocks = 0;
+};
+
 // Nine FP64 values passed by value to utility kernels (the storage shift).
 struct Shift9 {
   double v[9];

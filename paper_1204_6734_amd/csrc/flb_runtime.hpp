@@ -44,7 +44,7 @@ int finish_covariance(const Stats& S, const std::vector<double>& rec, const doub
 hipError_t launch_step(int storage, int compute, int basis, bool sample, int odd,
                        const SlotDesc* d_slots, const int* d_prefix, int nslots,
                        int total_tiles, const uint64_t* d_clock, uint32_t step_idx,
-                       hipStream_t st);
+                       LaunchCfg cfg, hipStream_t st);
 hipError_t launch_tick(uint64_t* d_clock, uint64_t n, hipStream_t st);
 hipError_t launch_write_state(int storage, void* pop, const double* f, int nx, int ny, int odd,
                               const Shift9& sh, int y0, int rows, hipStream_t st);

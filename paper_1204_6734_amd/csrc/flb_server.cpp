@@ -296,7 +296,8 @@ int flb_server::run_chunk() {
       const bool any_sample = due[c];
       // chunk_steps is even, so every request's own time has the parity of k
       HIPC(launch_step(storage, c, cfg.basis, any_sample, k & 1, d_slots[c], d_prefix[c],
-                       (int)members[c].size(), tiles[c], d_clock, (uint32_t)k, st));
+                       (int)members[c].size(), tiles[c], d_clock, (uint32_t)k, LaunchCfg{},
+                       st));
     }
     for (auto& a : active) {
       const uint64_t own = a.desc.t0 + clock + (uint64_t)k;

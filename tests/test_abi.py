@@ -69,3 +69,15 @@ def test_argument_errors_are_reported():
     assert codes[:3] == [F.E_ARG] * 3 and codes[3] == F.E_INVALID_VELOCITY
     assert lib.flb_lattice_bytes(C.byref(bad[0])) == 0
     assert lib.flb_lattice_bytes(C.byref(F.make_params(64, 64))) > 9 * 64 * 64 * 4
+
+
+def test_launch_config_layout_and_null_handles():
+    import paper_1204_6734_amd as F
+    lib = F.load()
+    assert C.sizeof(F.LaunchConfig) == 16 and F.LaunchConfig.ms_per_step.offset == 8
+    c = F.LaunchConfig(2, 64, 0.0)
+    n = C.c_int32()
+    assert lib.flb_lattice_autotune(None, 3, None, 0, C.byref(n)) == F.E_ARG
+    assert lib.flb_ensemble_autotune(None, 3, None, 0, C.byref(n)) == F.E_ARG
+    assert lib.flb_lattice_set_launch(None, C.byref(c)) == F.E_ARG
+    assert lib.flb_ensemble_get_launch(None, C.byref(c)) == F.E_ARG
