@@ -183,6 +183,29 @@ def collide(p: Params, f, site: int = 0, step: int = 0) -> np.ndarray:
 
 
 # ------------------------------------------------------------------- lattice
+def sk_fields(f: np.ndarray, rho0: float, ux0: float, uy0: float):
+    """The fields whose transforms the structure factors average (eqs. (24)-(26),
+    measured in the f-norm at (rho0, u0) as in the captions of Figs. 19-21):
+    d rho = sum_i f_i - rho0 and dM~^a = sum_i m~^a_i(u0) f_i (a = 1, 2) with
+    m~^1 = sqrt3 (v_x - u_x0), m~^2 = sqrt3 (v_y - u_y0), whose value at the
+    reference state is zero.  f: populations [9][ny][nx]."""
+    vx, vy, _ = velocities()
+    s3 = np.sqrt(3.0)
+    drho = f.sum(axis=0) - rho0
+    m1 = np.tensordot(s3 * (vx - ux0), f, axes=(0, 0))
+    m2 = np.tensordot(s3 * (vy - uy0), f, axes=(0, 0))
+    return drho, m1, m2
+
+
+def fourier_coefficient(a: np.ndarray, kx: int, ky: int) -> complex:
+    """A(k) = sum_x a(x) exp(-2 pi i (kx x / nx + ky y / ny)) of a field
+    a[ny][nx], by its definition (the separable sum)."""
+    ny, nx = a.shape
+    ex = np.exp(-2j * np.pi * ((kx * np.arange(nx)) % nx) / nx)
+    ey = np.exp(-2j * np.pi * ((ky * np.arange(ny)) % ny) / ny)
+    return complex(ey @ (a @ ex))
+
+
 class Lattice:
     """Host FP64 lattice mirroring the GPU library's lattice calls."""
 

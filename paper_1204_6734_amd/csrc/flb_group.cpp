@@ -59,13 +59,12 @@ void Group::layout(Arena& a) {
   band_rows = std::max(1, std::min(maxny, (int)((1u << 22) / (unsigned)maxnx)));
   d_io = a.take<double>((size_t)9 * band_rows * maxnx);
   if (n == 1 && P[0].sk_every > 0) {
-    const size_t N = max_sites;
-    d_skf = a.take<double>(3 * N);
-    d_z = a.take<double2>(2 * N);
-    d_zt = a.take<double2>(2 * N);
-    d_skacc = a.take<double>(5 * N);
-    d_twx = a.take<double2>(P[0].nx);
-    d_twy = a.take<double2>(P[0].ny);
+    const size_t N = max_sites, cplx = 2 * storage_size(storage);
+    d_z = a.take<char>(2 * N * cplx);
+    d_zt = a.take<char>(2 * N * cplx);
+    d_skacc = a.take<double>(5 * sk_half());
+    d_twx = a.take<char>(P[0].nx * cplx);
+    d_twy = a.take<char>(P[0].ny * cplx);
   }
 }
 
@@ -125,6 +124,13 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
   HIPC(hipGetDeviceProperties(&prop, dev_id));
   max_lds = prop.sharedMemPerBlock;
   device = dev_id;
+  if (d_skacc && (!sk_transform_supported(P[0].nx, storage, max_lds) ||
+                  !sk_transform_supported(P[0].ny, storage, max_lds)))
+    return set_error(FLB_E_ARG,
+                     "structure factors need sides that are powers of two up to %d (FP64) or "
+                     "%d (FP32) or at most %d",
+                     (int)(max_lds / sizeof(double2)), (int)(max_lds / sizeof(float2)),
+                     kMaxDirectDft);
   launch = tuned_launch(*this);
   // per-slot pointers and measurement bases
   mt0.assign(n, std::vector<double>(81));
@@ -132,7 +138,7 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
   for (int s = 0; s < n; ++s) {
     hdesc[s].pop = pop[s];
     hdesc[s].partials = d_partials[s];
-    hdesc[s].skf = d_skf;
+    hdesc[s].skz = d_z;
     hdesc[s].err = d_err + s;
     hdesc[s].err_step = d_err_step + s;
     hdesc[s].t0 = 0;
@@ -153,21 +159,24 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
   }
   if (d_skacc) {
     const int nx = P[0].nx, ny = P[0].ny;
-    HIPC(launch_fill(d_skacc, 5 * (size_t)nx * ny, 0.0, st));
-    // twiddles exp(-2 pi i k / n), k < n
-    std::vector<double2> tw(std::max(nx, ny));
+    HIPC(launch_fill(d_skacc, 5 * sk_half(), 0.0, st));
+    // twiddles exp(-2 pi i k / n), k < n, in the storage precision
     for (int dim = 0; dim < 2; ++dim) {
       const int m = dim == 0 ? nx : ny;
+      std::vector<double> tw(2 * (size_t)m);
+      std::vector<float> twf(2 * (size_t)m);
       for (int k = 0; k < m; ++k) {
         const double ph = -2.0 * M_PI * (double)k / (double)m;
-        tw[k] = make_double2(std::cos(ph), std::sin(ph));
+        tw[2 * k] = std::cos(ph);
+        tw[2 * k + 1] = std::sin(ph);
+        twf[2 * k] = (float)tw[2 * k];
+        twf[2 * k + 1] = (float)tw[2 * k + 1];
       }
-      HIPC(hipMemcpy(dim == 0 ? d_twx : d_twy, tw.data(), m * sizeof(double2),
+      const void* src = storage == 0 ? (const void*)tw.data() : (const void*)twf.data();
+      HIPC(hipMemcpy(dim == 0 ? d_twx : d_twy, src, 2 * (size_t)m * storage_size(storage),
                      hipMemcpyHostToDevice));
     }
-    const bool big = (is_pow2(nx) && (size_t)nx * 16 > 65536) ||
-                     (is_pow2(ny) && (size_t)ny * 16 > 65536);
-    if (big) HIPC(sk_prepare(max_lds));
+    HIPC(sk_prepare(max_lds));
   }
   for (int s = 0; s < n; ++s) {
     const flb_params& p = P[s];
@@ -211,7 +220,7 @@ bool Group::sk_due(int s, uint64_t tt) const {
 int Group::after_step(uint64_t tt) {
   for (int s = 0; s < (int)P.size(); ++s) {
     if (sk_due(s, tt)) {
-      HIPC(launch_sk_sample(d_skf, d_z, d_zt, d_skacc, P[s].nx, P[s].ny, d_twx, d_twy, max_lds,
+      HIPC(launch_sk_sample(storage, d_z, d_zt, d_skacc, P[s].nx, P[s].ny, d_twx, d_twy, max_lds,
                             st));
       nsk += 1;
     }
@@ -485,7 +494,7 @@ int Group::reset_stats() {
       HIPC(launch_fill(d_records[s], (size_t)kMaxTimeBlocks * kNStat, 0.0, st));
     }
   }
-  if (d_skacc) HIPC(launch_fill(d_skacc, 5 * (size_t)P[0].nx * P[0].ny, 0.0, st));
+  if (d_skacc) HIPC(launch_fill(d_skacc, 5 * sk_half(), 0.0, st));
   nsk = 0;
   HIPC(hipStreamSynchronize(st));
   return FLB_OK;
@@ -497,12 +506,21 @@ int Group::read_structure_factor(int which, double* out) {
   if (!d_skacc) return set_error(FLB_E_STATE, "structure factors are off (sk_every = 0)");
   if (which < 0 || which > 4) return set_error(FLB_E_ARG, "unknown structure factor %d", which);
   const int nx = P[0].nx, ny = P[0].ny;
-  const size_t N = (size_t)nx * ny;
-  std::vector<double> tmp(N);  // device order [kx][ky]
-  HIPC(hipMemcpy(tmp.data(), d_skacc + which * N, N * sizeof(double), hipMemcpyDeviceToHost));
-  const double norm = nsk > 0 ? 1.0 / ((double)nsk * (double)N) : 0.0;
+  const size_t H = sk_half();
+  std::vector<double> tmp(H);  // device order [kx][ky], kx <= nx/2
+  HIPC(hipMemcpy(tmp.data(), d_skacc + which * H, H * sizeof(double), hipMemcpyDeviceToHost));
+  const double norm = nsk > 0 ? 1.0 / ((double)nsk * (double)nx * (double)ny) : 0.0;
   for (int kx = 0; kx < nx; ++kx)
-    for (int ky = 0; ky < ny; ++ky) out[(size_t)ky * nx + kx] = tmp[(size_t)kx * ny + ky] * norm;
+    for (int ky = 0; ky < ny; ++ky) {
+      double v;
+      if (kx <= nx / 2) {
+        v = tmp[(size_t)kx * ny + ky];
+      } else {  // the value at -k: equal, or the conjugate for the cross term
+        v = tmp[(size_t)(nx - kx) * ny + (ky == 0 ? 0 : ny - ky)];
+        if (which == FLB_SK_JXJY_IM) v = -v;
+      }
+      out[(size_t)ky * nx + kx] = v * norm;
+    }
   return FLB_OK;
 }
 

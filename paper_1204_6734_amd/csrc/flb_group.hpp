@@ -38,12 +38,12 @@ struct Group {
   int band_rows = 1;
   std::vector<void*> pop;
   std::vector<double*> d_partials, d_records;
-  double* d_skf = nullptr;
-  double2* d_z = nullptr;
-  double2* d_zt = nullptr;
-  double* d_skacc = nullptr;
-  double2* d_twx = nullptr;
-  double2* d_twy = nullptr;
+  // structure factor: complex planes and twiddles in the storage precision
+  void* d_z = nullptr;
+  void* d_zt = nullptr;
+  double* d_skacc = nullptr;  // [5][nx/2 + 1][ny]
+  void* d_twx = nullptr;
+  void* d_twy = nullptr;
   // host state
   uint64_t t = 0, nsk = 0;
   int64_t err_step_host = -1;
@@ -91,6 +91,8 @@ struct Group {
   int restore(const void* host, size_t bytes);
   int kernel_time(double* ms, uint64_t* launches);
   void drop_graph();
+  // accumulator entries of one structure factor: the half plane kx <= nx/2
+  size_t sk_half() const { return (size_t)(P[0].nx / 2 + 1) * P[0].ny; }
   int set_launch(const flb_launch_config* c);
   int autotune(int reps, flb_launch_config* results, int max_results, int* n_results);
 };

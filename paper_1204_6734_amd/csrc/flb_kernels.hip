@@ -31,6 +31,11 @@
 
 namespace flb {
 
+// Complex value of a real type.
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+
 __device__ __forceinline__ int xcd_tile(int bid, int nb) {
   const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
   return xcd * q + (xcd < r ? xcd : r) + (bid >> 3);
@@ -272,18 +277,20 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
     const bool due = live && sd.sample_every > 0 && t % (uint64_t)sd.sample_every == 0;
     sample_correlators<R>(h, active, due, sd.partials + (size_t)(due ? lt : 0) * kNStat, sub,
                           wave);
-    if (live && sd.skf != nullptr && sd.sk_every > 0 && t % (uint64_t)sd.sk_every == 0 &&
+    if (live && sd.skz != nullptr && sd.sk_every > 0 && t % (uint64_t)sd.sk_every == 0 &&
         active) {
       // structure-factor fields in the f-norm at (rho0, u0): d rho and
-      // dj~ = sqrt3 (j - u0 rho) = sqrt3 ((j - rho0 u0) - u0 (rho - rho0))  (eq. (34))
+      // dj~ = sqrt3 (j - u0 rho) = sqrt3 ((j - rho0 u0) - u0 (rho - rho0))  (eq. (34)),
+      // packed as z1 = d rho + i dj~_x, z2 = dj~_y in the storage precision
+      using V = typename Cplx<S>::type;
       double hd[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) hd[i] = (double)h[i];
       const Moments<double> m = hermite_moments(hd);
       const uint32_t site = (uint32_t)y * nx + x;
-      sd.skf[site] = m.drho;
-      sd.skf[N + site] = 1.7320508075688772935 * (m.jx - sd.ux0 * m.drho);
-      sd.skf[2u * N + site] = 1.7320508075688772935 * (m.jy - sd.uy0 * m.drho);
+      V* z = reinterpret_cast<V*>(sd.skz);
+      z[site] = V{(S)m.drho, (S)(1.7320508075688772935 * (m.jx - sd.ux0 * m.drho))};
+      z[N + site] = V{(S)(1.7320508075688772935 * (m.jy - sd.uy0 * m.drho)), S(0)};
     }
   }
 
@@ -551,108 +558,243 @@ __global__ void fill_kernel(double* p, size_t n, double value) {
 }
 
 // -------------------------------------------------------- structure factor
-// Complex rows: z1 = d rho + i dj~_x, z2 = dj~_y (+ 0 i).
-__global__ void sk_pack_kernel(const double* __restrict__ f, double2* z, uint32_t N) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  z[i] = make_double2(f[i], f[N + i]);
-  z[N + i] = make_double2(f[2u * N + i], 0.0);
-}
+// The step kernel writes, on a structure-factor step, two complex planes
+// z1 = d rho + i dj~_x and z2 = dj~_y (+ 0 i) of the lattice's storage
+// precision T ([2][ny][nx]).  A 2-D FFT (rows, transpose, rows) follows, and
+// the squared magnitudes are accumulated in FP64 over the half plane
+// kx <= nx/2 (the other half follows from the fields being real).
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
+// multiplication by -i
+template <typename V> __device__ __forceinline__ V cmi(V a) { return V{a.y, -a.x}; }
 
-// In-LDS radix-2 decimation-in-time FFT of one row of length n (power of
-// two) per block: bit-reversed load, log2 n butterfly stages.  tw[k] =
-// exp(-2 pi i k / n), k < n/2.
-__global__ void fft_rows_pow2_kernel(const double2* __restrict__ in, double2* out, int n,
-                                     int logn, const double2* __restrict__ tw) {
-  extern __shared__ double2 buf[];
-  const size_t row = blockIdx.x;
-  const double2* src = in + row * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int r = (int)(__brev((unsigned)i) >> (32 - logn));
-    buf[r] = src[i];
+// In-register forward DFTs of 2, 4 and 8 points, out[r] = sum_s a[s]
+// exp(-2 pi i r s / R), natural order in and out.
+template <typename V> __device__ __forceinline__ void dft2(V* a) {
+  const V t = a[1];
+  a[1] = csub(a[0], t);
+  a[0] = cadd(a[0], t);
+}
+template <typename V> __device__ __forceinline__ void dft4(V* a) {
+  const V t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+  const V t2 = cadd(a[1], a[3]), t3 = cmi(csub(a[1], a[3]));
+  a[0] = cadd(t0, t2);
+  a[2] = csub(t0, t2);
+  a[1] = cadd(t1, t3);
+  a[3] = csub(t1, t3);
+}
+template <typename V> __device__ __forceinline__ void dft8(V* a) {
+  using T = decltype(a[0].x);
+  constexpr T h = T(0.70710678118654752440);
+  V e[4] = {a[0], a[2], a[4], a[6]}, o[4] = {a[1], a[3], a[5], a[7]};
+  dft4(e);
+  dft4(o);
+  // o[k] *= exp(-2 pi i k / 8)
+  o[1] = V{h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};
+  o[2] = cmi(o[2]);
+  o[3] = V{h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = cadd(e[k], o[k]);
+    a[k + 4] = csub(e[k], o[k]);
   }
-  __syncthreads();
-  for (int s = 1; s <= logn; ++s) {
-    const int half = 1 << (s - 1);
-    const int stride = n >> s;  // twiddle step
-    for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
-      const int grp = b / half, j = b - grp * half;
-      const int i0 = grp * 2 * half + j, i1 = i0 + half;
-      const double2 wv = tw[j * stride];
-      const double2 u = buf[i0], v = cmul(wv, buf[i1]);
-      buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-      buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+}
+template <int R, typename V> __device__ __forceinline__ void dft(V* a) {
+  if (R == 2) dft2(a);
+  if (R == 4) dft4(a);
+  if (R == 8) dft8(a);
+}
+
+// One Stockham pass of radix R over a row of length n held as E values per
+// thread (thread t owns butterflies j = t + m n/E, m < E/R).  Ns is the
+// length of the sub-transforms already done.  Input element j + r n/R of
+// butterfly j is twiddled by w^(r k n/(Ns R)) (k = j mod Ns, w = e^{-2 pi
+// i/n}) and transformed; output r goes to (j - k) R + k + r Ns.
+template <int R, int E, typename V>
+__device__ __forceinline__ void pass_load(V (&a)[E], const V* __restrict__ src, int n, int t) {
+  const int tpr = n / E;
+#pragma unroll
+  for (int m = 0; m < E / R; ++m)
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[m * R + r] = src[t + m * tpr + r * (n / R)];
+}
+
+template <int R, int E, typename V>
+__device__ __forceinline__ void pass_compute(V (&a)[E], int n, int t, int Ns,
+                                             const V* __restrict__ tw) {
+  const int tpr = n / E;
+#pragma unroll
+  for (int m = 0; m < E / R; ++m) {
+    if (Ns > 1) {
+      const int j = t + m * tpr;
+      const int step = (j & (Ns - 1)) * (n / (Ns * R));
+#pragma unroll
+      for (int r = 1; r < R; ++r) a[m * R + r] = cmul(a[m * R + r], tw[r * step]);
     }
-    __syncthreads();
+    dft<R>(&a[m * R]);
   }
-  double2* dst = out + row * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = buf[i];
 }
 
+template <int R, int E, typename V>
+__device__ __forceinline__ void pass_store(const V (&a)[E], V* dst, int n, int t, int Ns) {
+  const int tpr = n / E;
+#pragma unroll
+  for (int m = 0; m < E / R; ++m) {
+    const int j = t + m * tpr;
+    const int k = j & (Ns - 1);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = a[m * R + r];
+  }
+}
+
+// Pass of run-time radix R: phase 0 loads (when src is given) and
+// transforms, phase 1 stores.
+template <int E, typename V>
+__device__ __forceinline__ void fft_pass(int R, int phase, V (&a)[E], const V* src, V* dst,
+                                         int n, int t, int Ns, const V* tw) {
+  if (phase == 0) {
+    if (R == 8) {
+      if (src) pass_load<8, E>(a, src, n, t);
+      pass_compute<8, E>(a, n, t, Ns, tw);
+    } else if (R == 4) {
+      if (src) pass_load<4, E>(a, src, n, t);
+      pass_compute<4, E>(a, n, t, Ns, tw);
+    } else {
+      if (src) pass_load<2, E>(a, src, n, t);
+      pass_compute<2, E>(a, n, t, Ns, tw);
+    }
+  } else {
+    if (R == 8) pass_store<8, E>(a, dst, n, t, Ns);
+    else if (R == 4) pass_store<4, E>(a, dst, n, t, Ns);
+    else pass_store<2, E>(a, dst, n, t, Ns);
+  }
+}
+
+// Forward FFT of `rows` rows of length n = 2^logn >= 8 (out-of-place, natural
+// order), n / E threads per row and blockDim.x / (n / E) rows per workgroup,
+// each row staged in LDS between passes.  Passes: one of radix 2 or 4 if
+// logn is not a multiple of 3, then radix 8.  tw[m] = exp(-2 pi i m / n).
+template <typename T, int E>
+__global__ __launch_bounds__(1024) void fft_rows_kernel(const typename Cplx<T>::type* __restrict__ in,
+                                                       typename Cplx<T>::type* out, int n, int logn,
+                                                       int rows,
+                                                       const typename Cplx<T>::type* __restrict__ tw) {
+  using V = typename Cplx<T>::type;
+  extern __shared__ unsigned char fft_lds[];
+  const int tpr = n / E;
+  const int lr = threadIdx.x / tpr, t = threadIdx.x - lr * tpr;
+  const int rpb = blockDim.x / tpr;
+  const size_t row = (size_t)blockIdx.x * rpb + lr;
+  const bool have = row < (size_t)rows;
+  V* buf = reinterpret_cast<V*>(fft_lds) + (size_t)lr * n;
+  const V* src = in + (have ? row : 0) * n;
+  V* dst = out + (have ? row : 0) * n;
+  const int rem = logn % 3;
+  const int npass = logn / 3 + (rem ? 1 : 0);
+  V a[E];
+  int Ns = 1;
+  for (int p = 0; p < npass; ++p) {
+    const int R = (p == 0 && rem) ? (1 << rem) : 8;
+    if (p == 0) {
+      // from global memory; a row past the end transforms zeros
+      if (!have) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) a[e] = V{T(0), T(0)};
+      }
+      fft_pass<E, V>(R, 0, a, have ? src : nullptr, nullptr, n, t, Ns, tw);
+    } else {
+      fft_pass<E, V>(R, 0, a, buf, nullptr, n, t, Ns, tw);
+      __syncthreads();  // every read of this pass precedes its writes
+    }
+    if (p == npass - 1) {
+      if (have) fft_pass<E, V>(R, 1, a, nullptr, dst, n, t, Ns, tw);
+    } else {
+      fft_pass<E, V>(R, 1, a, nullptr, buf, n, t, Ns, tw);
+      __syncthreads();
+    }
+    Ns *= R;
+  }
+}
 // Direct DFT of rows of any length n: out[k] = sum_j in[j] tw[(j k) mod n],
-// tw[m] = exp(-2 pi i m / n), m < n.
-__global__ void dft_rows_kernel(const double2* __restrict__ in, double2* out, int n,
-                                const double2* __restrict__ tw) {
+// tw[m] = exp(-2 pi i m / n), m < n; sums in FP64.
+template <typename T>
+__global__ void dft_rows_kernel(const typename Cplx<T>::type* __restrict__ in,
+                                typename Cplx<T>::type* out, int n,
+                                const typename Cplx<T>::type* __restrict__ tw) {
+  using V = typename Cplx<T>::type;
   const size_t row = blockIdx.y;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const double2* src = in + row * n;
+  const V* src = in + row * n;
   double sr = 0.0, si = 0.0;
   int m = 0;
   for (int j = 0; j < n; ++j) {
-    const double2 a = src[j], wv = tw[m];
-    sr += a.x * wv.x - a.y * wv.y;
-    si += a.x * wv.y + a.y * wv.x;
+    const V a = src[j], wv = tw[m];
+    sr += (double)a.x * wv.x - (double)a.y * wv.y;
+    si += (double)a.x * wv.y + (double)a.y * wv.x;
     m += k;
     if (m >= n) m -= n;
   }
-  out[row * n + k] = make_double2(sr, si);
+  out[row * n + k] = V{(T)sr, (T)si};
 }
 
-// out[c][r] = in[r][c] for a rows x cols complex matrix (32 x 32 LDS tiles).
-__global__ void transpose_kernel(const double2* __restrict__ in, double2* out, int rows,
-                                 int cols) {
-  __shared__ double2 tile[32][33];
-  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+// out[c][r] = in[r][c] for gridDim.z matrices of rows x cols complex values,
+// through TILE x TILE tiles in LDS (256 threads; 32 for double2, 64 for
+// float2, 16 KB or 32 KB of LDS).
+template <typename V>
+__global__ __launch_bounds__(256) void transpose_kernel(const V* __restrict__ in, V* out,
+                                                        int rows, int cols) {
+  constexpr int TILE = sizeof(V) == 16 ? 32 : 64, STEP = 256 / TILE;
+  __shared__ V tile[TILE][TILE + 1];
+  const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
   const size_t z = blockIdx.z;
-  const double2* src = in + z * (size_t)rows * cols;
-  double2* dst = out + z * (size_t)rows * cols;
-  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
-    const int r = by + j, c = bx + threadIdx.x;
-    if (r < rows && c < cols) tile[j][threadIdx.x] = src[(size_t)r * cols + c];
+  const V* src = in + z * (size_t)rows * cols;
+  V* dst = out + z * (size_t)rows * cols;
+  const int tx = threadIdx.x % TILE, ty = threadIdx.x / TILE;
+#pragma unroll
+  for (int q = 0; q < TILE / STEP; ++q) {
+    const int j = ty + STEP * q, r = by + j, c = bx + tx;
+    if (r < rows && c < cols) tile[j][tx] = src[(size_t)r * cols + c];
   }
   __syncthreads();
-  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
-    const int c = bx + j, r = by + threadIdx.x;
-    if (r < rows && c < cols) dst[(size_t)c * rows + r] = tile[threadIdx.x][j];
+#pragma unroll
+  for (int q = 0; q < TILE / STEP; ++q) {
+    const int j = ty + STEP * q, c = bx + j, r = by + tx;
+    if (r < rows && c < cols) dst[(size_t)c * rows + r] = tile[tx][j];
   }
 }
 
 // Accumulate |d rho(k)|^2, |dj~_x(k)|^2, |dj~_y(k)|^2 and dj~_x(k) dj~_y(-k)
-// from the transformed packed fields, both stored transposed ([kx][ky]):
-// the accumulators keep that order so that consecutive threads touch
-// consecutive addresses.  With z1 = a + i b for real a, b:
-// a(k) = (Z1(k) + conj Z1(-k))/2, b(k) = (Z1(k) - conj Z1(-k))/(2i).
-__global__ void sk_accumulate_kernel(const double2* __restrict__ Zt, double* acc, int nx,
-                                     int ny) {
+// (real and imaginary part) over the half plane kx <= nx/2, from the
+// transformed planes stored transposed ([kx][ky]).  With z1 = a + i b for
+// real a, b: a(k) = (Z1(k) + conj Z1(-k))/2, b(k) = (Z1(k) - conj Z1(-k))/(2i);
+// likewise c(k) = (Z2(k) + conj Z2(-k))/2 for the real z2.  Each value is
+// thereby exactly the conjugate of its partner at -k.
+template <typename T>
+__global__ void sk_accumulate_kernel(const typename Cplx<T>::type* __restrict__ Zt, double* acc,
+                                     int nx, int ny) {
+  using V = typename Cplx<T>::type;
   const uint32_t N = (uint32_t)nx * ny;
+  const uint32_t H = (uint32_t)(nx / 2 + 1) * ny;  // half-plane size
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  if (i >= H) return;
   const int kx = (int)(i / (uint32_t)ny), ky = (int)(i - (uint32_t)kx * ny);
   const int mkx = kx == 0 ? 0 : nx - kx, mky = ky == 0 ? 0 : ny - ky;
-  const double2 z = Zt[i], zm = Zt[(uint32_t)mkx * ny + mky];
-  const double2 c = Zt[N + i];
-  const double ar = 0.5 * (z.x + zm.x), ai = 0.5 * (z.y - zm.y);
-  const double br = 0.5 * (z.y + zm.y), bi = -0.5 * (z.x - zm.x);
+  const uint32_t ip = (uint32_t)kx * ny + ky, im = (uint32_t)mkx * ny + mky;
+  const V z = Zt[ip], zm = Zt[im], c0 = Zt[N + ip], cm = Zt[N + im];
+  const double ar = 0.5 * ((double)z.x + zm.x), ai = 0.5 * ((double)z.y - zm.y);
+  const double br = 0.5 * ((double)z.y + zm.y), bi = -0.5 * ((double)z.x - zm.x);
+  const double cr = 0.5 * ((double)c0.x + cm.x), ci = 0.5 * ((double)c0.y - cm.y);
   acc[i] += ar * ar + ai * ai;
-  acc[N + i] += br * br + bi * bi;
-  acc[2u * N + i] += c.x * c.x + c.y * c.y;
-  acc[3u * N + i] += br * c.x + bi * c.y;   // Re(b conj c)
-  acc[4u * N + i] += bi * c.x - br * c.y;   // Im(b conj c)
+  acc[H + i] += br * br + bi * bi;
+  acc[2u * H + i] += cr * cr + ci * ci;
+  acc[3u * H + i] += br * cr + bi * ci;  // Re(b conj c)
+  acc[4u * H + i] += bi * cr - br * ci;  // Im(b conj c)
 }
 
 // ------------------------------------------------------------ launchers
@@ -828,44 +970,85 @@ static int ilog2(int n) {
   return l;
 }
 
-// Row transforms of `rows` rows of length n; tw holds n/2 entries for powers
-// of two (LDS path) and n entries otherwise (direct DFT).
-static hipError_t row_transform(const double2* in, double2* out, int n, int rows,
-                                const double2* tw, size_t max_lds, hipStream_t st) {
-  if (is_pow2(n) && (size_t)n * sizeof(double2) <= max_lds) {
-    const int threads = n / 2 < 1024 ? (n / 2 < 64 ? 64 : n / 2) : 1024;
-    const size_t lds = (size_t)n * sizeof(double2);
-    hipLaunchKernelGGL(fft_rows_pow2_kernel, dim3(rows), dim3(threads), lds, st, in, out, n,
-                       ilog2(n), tw);
+// Values per thread of the LDS FFT for a row of length n, or 0 when rows of
+// that length go through the direct DFT (not a power of two, shorter than
+// 8, or longer than the LDS holds).
+static int fft_values_per_thread(int n, size_t elem, size_t max_lds) {
+  if (!is_pow2(n) || n < 8 || (size_t)n * elem > max_lds) return 0;
+  return n <= 8192 ? 8 : (n <= 16384 ? 16 : 0);
+}
+
+int sk_transform_supported(int n, int storage, size_t max_lds) {
+  const size_t elem = storage == 0 ? sizeof(double2) : sizeof(float2);
+  return fft_values_per_thread(n, elem, max_lds) > 0 || n <= kMaxDirectDft;
+}
+
+template <typename T>
+static hipError_t row_transform(const typename Cplx<T>::type* in, typename Cplx<T>::type* out,
+                                int n, int rows, const typename Cplx<T>::type* tw, size_t max_lds,
+                                hipStream_t st) {
+  using V = typename Cplx<T>::type;
+  const int E = fft_values_per_thread(n, sizeof(V), max_lds);
+  if (E) {
+    const int tpr = n / E;
+    const int rpb = tpr >= 256 ? 1 : 256 / tpr;
+    const size_t lds = (size_t)rpb * n * sizeof(V);
+    const dim3 grid((rows + rpb - 1) / rpb), block(rpb * tpr);
+    if (E == 8) {
+      hipLaunchKernelGGL((fft_rows_kernel<T, 8>), grid, block, lds, st, in, out, n, ilog2(n),
+                         rows, tw);
+    } else {
+      // 16 values per thread: rows of 16384, which only FP32 fits in LDS
+      if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((fft_rows_kernel<T, 16>), grid, block, lds, st, in, out, n,
+                           ilog2(n), rows, tw);
+      else
+        return hipErrorInvalidValue;
+    }
   } else {
-    hipLaunchKernelGGL(dft_rows_kernel, dim3((n + 127) / 128, rows), dim3(128), 0, st, in, out,
+    hipLaunchKernelGGL(dft_rows_kernel<T>, dim3((n + 127) / 128, rows), dim3(128), 0, st, in, out,
                        n, tw);
   }
   return hipGetLastError();
 }
 
 hipError_t sk_prepare(size_t max_lds) {
-  return hipFuncSetAttribute((const void*)fft_rows_pow2_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+  const void* k[] = {(const void*)fft_rows_kernel<double, 8>, (const void*)fft_rows_kernel<float, 8>,
+                     (const void*)fft_rows_kernel<float, 16>};
+  for (const void* f : k) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-// Full structure-factor sample: fields (already written by the step kernel)
-// -> packed complex rows -> x transforms -> transpose -> y transforms ->
-// accumulate.  z, zt: 2 N complex scratch each.
-hipError_t launch_sk_sample(const double* fields, double2* z, double2* zt, double* acc, int nx,
-                            int ny, const double2* twx, const double2* twy, size_t max_lds,
-                            hipStream_t st) {
-  const uint32_t N = (uint32_t)nx * ny;
-  hipLaunchKernelGGL(sk_pack_kernel, dim3((N + 255) / 256), dim3(256), 0, st, fields, z, N);
-  hipError_t e = row_transform(z, zt, nx, 2 * ny, twx, max_lds, st);
+template <typename T>
+static hipError_t sk_sample_t(void* z, void* zt, double* acc, int nx, int ny, const void* twx,
+                              const void* twy, size_t max_lds, hipStream_t st) {
+  using V = typename Cplx<T>::type;
+  V* a = (V*)z;
+  V* b = (V*)zt;
+  hipError_t e = row_transform<T>(a, b, nx, 2 * ny, (const V*)twx, max_lds, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(transpose_kernel, dim3((nx + 31) / 32, (ny + 31) / 32, 2), dim3(32, 8), 0,
-                     st, zt, z, ny, nx);
-  e = row_transform(z, zt, ny, 2 * nx, twy, max_lds, st);
+  constexpr int TILE = sizeof(V) == 16 ? 32 : 64;
+  hipLaunchKernelGGL(transpose_kernel<V>, dim3((nx + TILE - 1) / TILE, (ny + TILE - 1) / TILE, 2),
+                     dim3(256), 0, st, b, a, ny, nx);
+  e = row_transform<T>(a, b, ny, 2 * nx, (const V*)twy, max_lds, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sk_accumulate_kernel, dim3((N + 255) / 256), dim3(256), 0, st, zt, acc, nx,
+  const uint32_t H = (uint32_t)(nx / 2 + 1) * ny;
+  hipLaunchKernelGGL(sk_accumulate_kernel<T>, dim3((H + 255) / 256), dim3(256), 0, st, b, acc, nx,
                      ny);
   return hipGetLastError();
+}
+
+// One structure-factor sample.  z holds the planes the step kernel wrote
+// ([2][ny][nx], storage precision) and is overwritten; zt is scratch of the
+// same size; twx / twy are the twiddle tables (storage precision, nx and ny
+// entries); acc: 5 (nx/2 + 1) ny FP64 accumulators, [which][kx][ky].
+hipError_t launch_sk_sample(int storage, void* z, void* zt, double* acc, int nx, int ny,
+                            const void* twx, const void* twy, size_t max_lds, hipStream_t st) {
+  if (storage == 0) return sk_sample_t<double>(z, zt, acc, nx, ny, twx, twy, max_lds, st);
+  return sk_sample_t<float>(z, zt, acc, nx, ny, twx, twy, max_lds, st);
 }
 
 }  // namespace flb

@@ -14,6 +14,7 @@ constexpr int kMaxTilesPerBlock = 4;  // workgroups of up to 1024 threads
 constexpr int kMaxBlock = kBlock * kMaxTilesPerBlock;
 constexpr int kNStat = 54;   // 9 first moments + 45 unique second moments
 constexpr int kMaxTimeBlocks = 1024;
+constexpr int kMaxDirectDft = 4096;  // longest row transformed by the O(n^2) DFT
 enum : int { kErrInvalidVelocity = 1, kErrNonFinite = 2 };
 
 // One lattice ("slot") as seen by the batched step kernel.  All slots of a
@@ -21,7 +22,7 @@ enum : int { kErrInvalidVelocity = 1, kErrNonFinite = 2 };
 struct SlotDesc {
   void* pop;            // storage [9][ny][nx], shifted h = f - f^0(rho0, u0)
   double* partials;     // [ntiles][kNStat] open time-block sums (sampling)
-  double* skf;          // [3][ny][nx] structure-factor fields or null
+  void* skz;            // [2][ny][nx] complex structure-factor planes (storage precision) or null
   int* err;             // error bits (atomicOr)
   unsigned long long* err_step;  // first failing step (atomicMin)
   int nx, ny, tiles_x, ntiles;

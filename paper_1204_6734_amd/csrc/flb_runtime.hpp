@@ -67,9 +67,11 @@ hipError_t launch_merge_blocks(double* rec, int nhalf, hipStream_t st);
 hipError_t launch_open_sum(const double* partials, int ntiles, double* out, hipStream_t st);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
 hipError_t sk_prepare(size_t max_lds);
-hipError_t launch_sk_sample(const double* fields, double2* z, double2* zt, double* acc, int nx,
-                            int ny, const double2* twx, const double2* twy, size_t max_lds,
-                            hipStream_t st);
+hipError_t launch_sk_sample(int storage, void* z, void* zt, double* acc, int nx, int ny,
+                            const void* twx, const void* twy, size_t max_lds, hipStream_t st);
+// Whether rows of length n can be transformed (power of two that fits the
+// LDS FFT, or short enough for the direct DFT).
+int sk_transform_supported(int n, int storage, size_t max_lds);
 
 // Bump allocator over one device allocation (256-byte aligned pieces).
 struct Arena {

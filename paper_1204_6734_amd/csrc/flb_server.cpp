@@ -185,7 +185,7 @@ int flb_server::admit_locked() {
                                            : nullptr;
     a.desc.err = (int*)take(8);
     a.desc.err_step = (unsigned long long*)(a.desc.err + 2);
-    a.desc.skf = nullptr;
+    a.desc.skz = nullptr;
     a.desc.t0 = (uint64_t)0 - clock;  // own time 0 at the current server clock
     a.desc.tend = a.nsteps;
     a.stats.reset(a.p.block_steps);

@@ -78,3 +78,47 @@ def test_8192_fp32_shear_wave_decay_and_conservation(flb):
     m1 = [L.fourier_mode(w, 0, 0) for w in range(3)]
     for a, b in zip(m0, m1):
         assert abs(a - b) <= 1e-6 * nx * ny
+
+
+def test_8192_fp32_structure_factor_sampled_k(flb):
+    """One S(k) sample of the 8192 x 8192 FP32 lattice (thermal start, the
+    state at t = 0) against the Fourier sums of the oracle's field
+    definitions, evaluated at sampled wave vectors of every kind (k = 0,
+    Nyquist, both half planes, random)."""
+    nx = ny = 8192
+    kw = dict(ux0=0.1, kT=1e-4, seed=5)
+    L = flb.Lattice(flb.make_params(nx, ny, precision=flb.FP32_SHIFTED, init=flb.INIT_THERMAL,
+                                    sk_every=1000, **kw))
+    f = L.populations()
+    L.step(1)
+    fields = O.sk_fields(f, 1.0, 0.1, 0.0)
+    del f
+    S = [L.structure_factor(w) for w in range(5)]
+    rng = np.random.default_rng(2)
+    ks = [(0, 0), (1, 0), (0, 1), (nx // 2, ny // 2), (nx - 1, 3), (4095, 8191), (4097, 1)]
+    ks += [(int(a), int(b)) for a, b in zip(rng.integers(0, nx, 12), rng.integers(0, ny, 12))]
+    want = np.empty((len(ks), 5))
+    for n, (kx, ky) in enumerate(ks):
+        A, B, Cc = (O.fourier_coefficient(g, kx, ky) for g in fields)
+        want[n] = [abs(A) ** 2, abs(B) ** 2, abs(Cc) ** 2, (B * Cc.conjugate()).real,
+                   (B * Cc.conjugate()).imag]
+    want /= nx * ny
+    got = np.array([[S[w][ky, kx] for w in range(5)] for kx, ky in ks])
+    scale = np.abs(want[1:, :3]).mean()  # typical |A|^2 / N away from k = 0
+    err = np.abs(got - want).max() / scale
+    print(f"8192^2 FP32 S(k): max error / typical S = {err:.2e}")
+    assert err < 1e-4
+
+
+def test_16384_row_fp32_structure_factor_matches_oracle(flb):
+    """Rows of 16384 (the 16-values-per-thread FFT) in FP32 against the
+    oracle, one sample of a thermal state."""
+    nx, ny = 16384, 3
+    kw = dict(ux0=0.05, kT=1e-4, seed=6, init=flb.INIT_THERMAL, sk_every=1000)
+    g = flb.Lattice(flb.make_params(nx, ny, precision=flb.FP32_SHIFTED, **kw))
+    o = O.Lattice(O.make_params(nx, ny, **kw))
+    g.step(1)
+    o.step(1)
+    scale = np.abs(o.structure_factor(0)).max()
+    for w in range(5):
+        assert np.abs(g.structure_factor(w) - o.structure_factor(w)).max() <= 2e-5 * scale, w

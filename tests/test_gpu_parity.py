@@ -95,15 +95,23 @@ def test_time_block_merge_matches_oracle(flb):
         assert np.abs(cg[k] - co[k]).max() <= 1e-9 * np.abs(co[k]).max(), k
 
 
-@pytest.mark.parametrize("nx,ny", [(16, 8), (12, 10), (64, 32)])
-def test_structure_factor_matches_oracle(flb, nx, ny):
+@pytest.mark.parametrize("prec,nx,ny", [("fp64", 16, 8), ("fp64", 12, 10), ("fp64", 64, 32),
+                                         ("fp64", 8, 1024), ("fp32", 64, 32), ("fp32", 12, 10),
+                                         ("fp32", 256, 16)])
+def test_structure_factor_matches_oracle(flb, prec, nx, ny):
+    """S(k) of all five kinds against the oracle: FFT sizes from 8 to 1024
+    (radix-8 passes after a radix-2 or -4 one), direct DFTs for other
+    sizes.  FP32-shifted lattices transform in FP32 (accumulators FP64)."""
+    precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+    tol = 1e-10 if prec == "fp64" else 2e-5
     kw = dict(ux0=0.1, kT=1e-4, seed=9, sk_every=3)
-    g, o = both(flb, nx, ny, flb.FP64, **kw)
+    g, o = both(flb, nx, ny, precision, **kw)
     g.step(40)
     o.step(40)
+    scale = np.abs(o.structure_factor(0)).max()
     for w in range(5):
         sg, so = g.structure_factor(w), o.structure_factor(w)
-        assert np.abs(sg - so).max() <= 1e-10 * np.abs(o.structure_factor(0)).max(), w
+        assert np.abs(sg - so).max() <= tol * scale, w
 
 
 def test_fourier_mode_matches_oracle(flb):

@@ -483,3 +483,37 @@ def test_structure_factor_matches_theory():
         ratio = got[mask].mean() / want[mask].mean()
         assert abs(ratio - 1) < 0.03, (key, ratio)
         assert abs(want[mask].mean() / mu - 1) < 0.3
+
+
+def test_fourier_coefficient_is_the_dft():
+    """The definition-level Fourier sum equals numpy's FFT (a library
+    routine), including negative and wrapped wave numbers."""
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal((6, 10))
+    F = np.fft.fft2(a)
+    for kx, ky in [(0, 0), (3, 2), (9, 5), (-1, 1), (13, -4)]:
+        assert abs(O.fourier_coefficient(a, kx, ky) - F[ky % 6, kx % 10]) < 1e-12
+
+
+def test_sk_fields_and_single_sample_structure_factor():
+    """One structure-factor sample of the oracle lattice (its C code) equals
+    |A(k)|^2 / (nx ny) of the fields built here from its populations, and the
+    fields vanish for the reference equilibrium."""
+    rho0, ux0, uy0 = 1.3, 0.1, -0.05
+    f0 = np.stack([O.equilibrium(rho0, ux0, uy0)[i] * np.ones((4, 6)) for i in range(9)])
+    for g in O.sk_fields(f0, rho0, ux0, uy0):
+        assert np.abs(g).max() < 1e-14
+    nx, ny = 10, 6
+    p = O.make_params(nx, ny, rho0=rho0, ux0=ux0, uy0=uy0, kT=1e-4, seed=3, init=O.INIT_THERMAL,
+                      sk_every=1000)
+    L = O.Lattice(p)
+    f = L.populations()
+    L.step(1)  # samples the state at t = 0
+    d, m1, m2 = O.sk_fields(f, rho0, ux0, uy0)
+    S = [L.structure_factor(w) for w in range(5)]
+    for kx, ky in [(0, 0), (1, 0), (3, 2), (9, 5), (5, 3)]:
+        A, B, Cc = (O.fourier_coefficient(g, kx, ky) for g in (d, m1, m2))
+        want = [abs(A) ** 2, abs(B) ** 2, abs(Cc) ** 2, (B * Cc.conjugate()).real,
+                (B * Cc.conjugate()).imag]
+        for w in range(5):
+            assert abs(S[w][ky, kx] - want[w] / (nx * ny)) < 1e-12 * (abs(A) ** 2 + 1e-3), (w, kx, ky)
