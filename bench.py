@@ -33,8 +33,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"f32": 72, "f64": 144}
+# sources of the step kernel (the one whose HBM traffic the profiles record)
 KERNEL_SOURCES = ["paper_1204_6734_amd/csrc/flb_device.hpp",
-                  "paper_1204_6734_amd/csrc/flb_kernels.hip",
+                  "paper_1204_6734_amd/csrc/flb_step.hip",
                   "paper_1204_6734_amd/csrc/flb_kernels.hpp"]
 
 
@@ -88,14 +89,16 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
     L.set_fields(*I.shear_wave_fields(nx, nx, ux0=0.1, amp=1e-3))
     tune = L.autotune(reps=3)  # trial steps run on a copy of the state
 
+    chunk = every if every > 0 else 100
+
     def run(n):
         done = 0
         log = []
         while done < n:
-            k = min(every, n - done)
+            k = min(chunk, n - done)
             L.step(k)
             done += k
-            if done % every == 0:
+            if every > 0 and done % every == 0:
                 log.append(L.fourier_mode(2, 1, 0))
         return log
 
@@ -115,11 +118,12 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
             "mode_log": [abs(z) for z in log[-3:]],
             "launch": {"chosen": L.get_launch(), "candidates": tune},
             "config": {"workload": f"{nx}x{nx} D2Q9 FP32-shifted, rho0=1, u_x0=0.1, kT=1e-4, "
-                                   f"tau=1, shear wave 1e-3 sin(2 pi x/L); S(k) and "
-                                   f"j~_y(2 pi/L) every {every} steps",
+                                   f"tau=1, shear wave 1e-3 sin(2 pi x/L); " +
+                                   (f"S(k) and j~_y(2 pi/L) every {every} steps" if every > 0
+                                    else "no S(k), no mode log"),
                        "nx": nx, "ny": nx, "precision": "fp32_shifted", "basis": "fnorm_local",
                        "sk_every": every, "parallelism": "single GPU"},
-            "dtype": "f32", "kernel_name": "step_fp32_8192"}
+            "dtype": "f32", "kernel_name": f"step_fp32_{nx}"}
 
 
 def run_ensemble(F, torch, steps: int, warmup: int, n: int = 64, side: int = 128,
@@ -176,6 +180,12 @@ def run_serving(F, torch, nreq: int = 40, rate: float = 50.0, chunk: int = 100,
             time.sleep(0.0005)
         S.submit(params(r, F.FP32_SHIFTED), r["nsteps"], tag=k)
     print(f"serving: {nreq} requests submitted", file=sys.stderr, flush=True)
+    last = time.perf_counter()
+    while S.stats()["completed"] < nreq:
+        time.sleep(0.01)
+        if time.perf_counter() - last > 10:
+            last = time.perf_counter()
+            print(f"serving: {S.stats()['completed']}/{nreq} done", file=sys.stderr, flush=True)
     S.drain()
     print("serving: drained", file=sys.stderr, flush=True)
     res = S.poll(nreq + 8)
@@ -233,6 +243,9 @@ def main():
                     help="serving window (default 40 in the main line, 400 with --workload serve)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--nx", type=int, default=8192)
+    ap.add_argument("--sk-every", type=int, default=100,
+                    help="structure-factor and mode-log interval of the large workload (0: off)")
+    ap.add_argument("--rate", type=float, default=50.0, help="serving arrival rate (1/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -256,10 +269,10 @@ def main():
         print(json.dumps({"workload": "64 x 128^2 FP32 ensemble, hipGraph", **r}), flush=True)
         return
     if args.workload == "serve":
-        r = run_serving(F, torch, nreq=args.requests or 400)
+        r = run_serving(F, torch, nreq=args.requests or 400, rate=args.rate)
         print(json.dumps({"workload": "serving, Poisson 50/s", **r}), flush=True)
         return
-    r = run_large(F, torch, args.steps, args.warmup, nx=args.nx)
+    r = run_large(F, torch, args.steps, args.warmup, nx=args.nx, every=args.sk_every)
     mlups = r["sites"] * args.steps / r["dt"] / 1e6
     bps = BYTES_PER_SITE[r["dtype"]]
     achieved = bps * r["sites"] / (r["kernel_ms"] * 1e-3) / 1e9

@@ -1,26 +1,7 @@
-// flb_kernels.hip — HIP kernels of libflb for gfx950 (MI355X).
-//
-// The hot kernel is step_kernel: one fused fluctuating collide-and-stream
-// update (Kaehler & Wagner, Sec. II eq. (6) with the f-norm basis of
-// Sec. IV) over every site of one or more lattices ("slots"), with the
-// correlator sums of eqs. (16)/(23) and the structure-factor fields of
-// eqs. (24)-(26) fused in when a sample is due.
-//
-// Memory layout: one population array per lattice, structure of arrays
-// [9][ny][nx] of shifted values h_i = f_i - w_i rho0 (FP32 or FP64), updated
-// in place with the two-phase "AA" access pattern: on even steps a site
-// reads its own nine slots and writes the post-collision values back
-// reversed; on odd steps it reads the reversed values of its neighbours and
-// writes forward to its neighbours.  Each site touches the same nine
-// locations it reads, so no second buffer is needed.  The unit of work is a
-// 64 x 4 tile (256 threads, one wavefront per tile row: every wavefront reads
-// and writes whole rows).  A workgroup takes 1, 2 or 4 consecutive tiles
-// ("tile group"), and the grid is either one workgroup per tile group or a
-// smaller persistent grid striding over the tile groups; the autotuner picks
-// among these shapes, which all compute bit-identical results.  Tile groups
-// are renumbered so that each XCD (workgroups are dealt to the eight XCDs
-// round-robin) sweeps a contiguous band of rows and keeps its halo rows in
-// its own L2.
+// flb_kernels.hip — utility kernels of libflb for gfx950 (MI355X): state
+// input and output, moments, Fourier modes, time-block bookkeeping of the
+// correlator sums, and the structure-factor transforms (eqs. (24)-(26)).
+// The step kernel itself is in flb_step.hip.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,25 +11,6 @@
 #include "flb_kernels.hpp"
 
 namespace flb {
-
-// Complex value of a real type.
-template <typename T> struct Cplx;
-template <> struct Cplx<double> { using type = double2; };
-template <> struct Cplx<float> { using type = float2; };
-
-__device__ __forceinline__ int xcd_tile(int bid, int nb) {
-  const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
-  return xcd * q + (xcd < r ? xcd : r) + (bid >> 3);
-}
-
-__device__ __forceinline__ int find_slot(const int* __restrict__ prefix, int nslots, int tile) {
-  int lo = 0, hi = nslots;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (prefix[mid] <= tile) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 // Element indices of the nine populations a site reads in phase `odd`.
 // After the collision the value of direction kOpp[i] goes back to idx[i].
@@ -74,278 +36,6 @@ __device__ __forceinline__ void site_indices(int x, int y, int nx, int ny, int o
     idx[8] = 6u * N + rp + xm;   // v=( 1,-1): plane 6 at (x-1, y+1)
   }
 }
-
-template <typename R>
-__device__ __forceinline__ CollideConst<R> collide_const(const SlotDesc& sd);
-
-template <>
-__device__ __forceinline__ CollideConst<float> collide_const<float>(const SlotDesc& sd) {
-  CollideConst<float> C;
-  C.rho0 = sd.rho0f;
-  C.ux0 = sd.ux0f;
-  C.uy0 = sd.uy0f;
-#pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    C.rt[a] = sd.rtf[a];
-    C.xc[a] = sd.xcf[a];
-  }
-  C.k0 = sd.k0;
-  C.k1 = sd.k1;
-  C.noise = sd.noise;
-  return C;
-}
-
-template <>
-__device__ __forceinline__ CollideConst<double> collide_const<double>(const SlotDesc& sd) {
-  CollideConst<double> C;
-  C.rho0 = sd.rho0;
-  C.ux0 = sd.ux0;
-  C.uy0 = sd.uy0;
-#pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    C.rt[a] = sd.rt[a];
-    C.xc[a] = sd.xc[a];
-  }
-  C.k0 = sd.k0;
-  C.k1 = sd.k1;
-  C.noise = sd.noise;
-  return C;
-}
-
-// Sums of 32 per-lane values over a 64-lane wavefront, transposed: five
-// butterfly passes each halve the number of values a lane carries and a
-// last pass adds the two lanes that share a value, after which lanes 2v and
-// 2v+1 both hold the wave total of value v.
-__device__ __forceinline__ double pick(uint64_t mask, double a, double b) {
-  // a where mask is all ones, b where it is zero (bitwise, so the choice is
-  // never turned into a dynamically indexed array access)
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  return __builtin_bit_cast(double, (ua & mask) | (ub & ~mask));
-}
-
-__device__ __forceinline__ double wave_transpose_sum32(double (&v)[32], int lane) {
-#pragma unroll
-  for (int off = 32, n = 16; off >= 2; off >>= 1, n >>= 1) {
-    const uint64_t up = (lane & off) ? ~0ull : 0ull;
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-      const double send = pick(up, v[k], v[k + n]);
-      const double keep = pick(up, v[k + n], v[k]);
-      v[k] = keep + __shfl_xor(send, off, 64);
-    }
-  }
-  return v[0] + __shfl_xor(v[0], 1, 64);
-}
-
-// Correlator sums of df_i = f_i - f_i^0(rho0, u0) (= the stored h_i): 9
-// first moments and the 45 products i <= j (row-major), added to this
-// tile's open time-block partials.  Reduced in two groups of 32 values to
-// keep registers low.  Every thread of the workgroup calls this (it holds
-// two workgroup barriers); `due` is uniform over one tile and says whether
-// the tile samples at all.  The partial of a tile is always formed in the
-// same order, whatever the workgroup shape.
-template <typename R>
-__device__ __forceinline__ void sample_correlators(const R h[9], bool active, bool due,
-                                                   double* __restrict__ partials, int sub,
-                                                   int wave) {
-  __shared__ double red[kMaxTilesPerBlock][kTileY][kTileX];
-  const int lane = threadIdx.x & 63;
-  if (due) {
-    double df[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) df[i] = active ? (double)h[i] : 0.0;
-#pragma unroll
-    for (int group = 0; group < 2; ++group) {
-      double v[32];
-      int k = 0, q = 0;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        if (q >= group * 32 && q < group * 32 + 32) v[k++] = df[i];
-        ++q;
-      }
-#pragma unroll
-      for (int i = 0; i < 9; ++i)
-#pragma unroll
-        for (int j = i; j < 9; ++j) {
-          if (q >= group * 32 && q < group * 32 + 32) v[k++] = df[i] * df[j];
-          ++q;
-        }
-#pragma unroll
-      for (; k < 32; ++k) v[k] = 0.0;
-      const double tot = wave_transpose_sum32(v, lane);
-      if ((lane & 1) == 0) red[sub][wave][group * 32 + (lane >> 1)] = tot;
-    }
-  }
-  __syncthreads();
-  const int v = threadIdx.x & (kBlock - 1);
-  if (due && v < kNStat) {
-    const double tot = (red[sub][0][v] + red[sub][1][v]) + (red[sub][2][v] + red[sub][3][v]);
-    partials[v] += tot;
-  }
-  __syncthreads();  // red is reused by the next tile group of a persistent grid
-}
-
-// Byte offsets (within their planes) of the nine populations a site reads
-// in phase ODD, with the plane each one lives in.  Even phase: plane i at
-// the site itself.  Odd phase: plane opp(i) at x - v_i.  After the
-// collision the value of direction kOpp[i] goes back to the same place.
-// Rows are wave-uniform (one wavefront = 64 sites of one row), so only the
-// x wrap is per lane.
-template <typename S, int ODD>
-__device__ __forceinline__ void site_offsets(int x, int y, int nx, int ny, uint32_t off[9]) {
-  constexpr uint32_t E = sizeof(S);
-  const uint32_t rc = (uint32_t)y * nx * E;
-  const uint32_t xc = (uint32_t)x * E;
-  if (!ODD) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) off[i] = rc + xc;
-  } else {
-    const uint32_t rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx * E;
-    const uint32_t rp = (uint32_t)(y == ny - 1 ? 0 : y + 1) * nx * E;
-    const uint32_t xm = x == 0 ? (uint32_t)(nx - 1) * E : xc - E;
-    const uint32_t xp = x == nx - 1 ? 0u : xc + E;
-    off[0] = rc + xc;
-    off[1] = rc + xm;  // v=( 1, 0) from (x-1, y)
-    off[2] = rm + xc;  // v=( 0, 1) from (x, y-1)
-    off[3] = rc + xp;  // v=(-1, 0) from (x+1, y)
-    off[4] = rp + xc;  // v=( 0,-1) from (x, y+1)
-    off[5] = rm + xm;  // v=( 1, 1) from (x-1, y-1)
-    off[6] = rm + xp;  // v=(-1, 1) from (x+1, y-1)
-    off[7] = rp + xp;  // v=(-1,-1) from (x+1, y+1)
-    off[8] = rp + xm;  // v=( 1,-1) from (x-1, y+1)
-  }
-}
-
-// Raw buffer access to one population plane: the 128-bit resource (base,
-// size) is wave-uniform and lives in SGPRs, the per-lane byte offset is a
-// 32-bit VGPR, so no per-lane 64-bit address arithmetic is needed.  An
-// offset outside the plane reads zero and drops the store.
-template <typename S>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(void* pop, uint32_t N, int k) {
-  char* base = reinterpret_cast<char*>(pop) + (size_t)k * N * sizeof(S);
-  return __builtin_amdgcn_make_buffer_rsrc(base, 0, N * (uint32_t)sizeof(S), 0x00020000);
-}
-
-__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, float*) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, double*) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
-}
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
-}
-
-// One tile (or none: tile < 0) of the batched step.  A tile of a slot whose
-// own time has reached its end is skipped; with SAMPLE the caller's whole
-// workgroup still passes the barriers of the correlator reduction.
-template <typename S, typename R, int BASIS, bool SAMPLE, int ODD>
-__device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
-                                          const int* __restrict__ prefix, int nslots, int tile,
-                                          uint64_t clk, int sub, int wave) {
-  const bool have = tile >= 0;
-  const int s = have ? find_slot(prefix, nslots, tile) : 0;
-  const SlotDesc& sd = slots[s];
-  const uint64_t t = sd.t0 + clk;
-  const bool live = have && t < sd.tend;
-  if (!SAMPLE && !live) return;
-  const int lt = tile - prefix[s];
-  const int nx = sd.nx, ny = sd.ny;
-  const int ty = lt / sd.tiles_x, tx = lt - ty * sd.tiles_x;
-  const int x = tx * kTileX + (threadIdx.x & (kTileX - 1));
-  const int y = ty * kTileY + wave;
-  const bool active = live && (x < nx) && (y < ny);
-  const uint32_t N = (uint32_t)nx * (uint32_t)ny;
-
-  uint32_t off[9];
-  R h[9];
-  if (active) {
-    site_offsets<S, ODD>(x, y, nx, ny, off);
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-      h[i] = (R)buf_load(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), off[i], (S*)nullptr);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) h[i] = R(0);
-  }
-
-  if (SAMPLE) {
-    const bool due = live && sd.sample_every > 0 && t % (uint64_t)sd.sample_every == 0;
-    sample_correlators<R>(h, active, due, sd.partials + (size_t)(due ? lt : 0) * kNStat, sub,
-                          wave);
-    if (live && sd.skz != nullptr && sd.sk_every > 0 && t % (uint64_t)sd.sk_every == 0 &&
-        active) {
-      // structure-factor fields in the f-norm at (rho0, u0): d rho and
-      // dj~ = sqrt3 (j - u0 rho) = sqrt3 ((j - rho0 u0) - u0 (rho - rho0))  (eq. (34)),
-      // packed as z1 = d rho + i dj~_x, z2 = dj~_y in the storage precision
-      using V = typename Cplx<S>::type;
-      double hd[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) hd[i] = (double)h[i];
-      const Moments<double> m = hermite_moments(hd);
-      const uint32_t site = (uint32_t)y * nx + x;
-      V* z = reinterpret_cast<V*>(sd.skz);
-      z[site] = V{(S)m.drho, (S)(1.7320508075688772935 * (m.jx - sd.ux0 * m.drho))};
-      z[N + site] = V{(S)(1.7320508075688772935 * (m.jy - sd.uy0 * m.drho)), S(0)};
-    }
-  }
-
-  if (!active) return;
-  const CollideConst<R> C = collide_const<R>(sd);
-  const uint32_t site = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
-  const int e = collide<R, BASIS>(h, C, site, t);
-  if (e) {
-    atomicOr(sd.err, e);
-    atomicMin(sd.err_step, (unsigned long long)t);
-  }
-#pragma unroll
-  for (int i = 0; i < 9; ++i)
-    buf_store(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), off[i], (S)h[kOpp[i]]);
-}
-
-// Tiles per workgroup a step variant accepts: the sampling variants and the
-// FP64-compute variants need more than 128 registers, so they take at most
-// two (a 1024-thread workgroup caps a thread at 128).
-template <typename R, bool SAMPLE>
-constexpr int max_tiles_per_block() {
-  return (SAMPLE || sizeof(R) == 8) ? 2 : kMaxTilesPerBlock;
-}
-
-// The batched step: blockDim.x / 256 tiles per workgroup.  Without PERSIST
-// workgroup b takes tile group b; with PERSIST (a grid smaller than the
-// number of tile groups, and a multiple of eight so that a tile group stays
-// on the XCD its renumbering assumes) it takes tile groups b, b + gridDim.x,
-// ...  Only non-sampling steps run persistent (a loop around the reduction
-// doubles its register use), and the one-group-per-workgroup variant keeps
-// no loop at all, which measured about 3 % faster on the large lattice.
-template <typename S, typename R, int BASIS, bool SAMPLE, int ODD, bool PERSIST>
-__global__ __launch_bounds__((kBlock * max_tiles_per_block<R, SAMPLE>())) void step_kernel(
-    const SlotDesc* __restrict__ slots, const int* __restrict__ prefix, int nslots,
-    int total_tiles, const uint64_t* __restrict__ clock, uint32_t step_idx) {
-  static_assert(!(SAMPLE && PERSIST), "sampling steps are not persistent");
-  const int lg = blockDim.x >> 9;  // log2 of the tiles per workgroup
-  const int ngroups = (total_tiles + (1 << lg) - 1) >> lg;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int sub = wid >> 2, wave = wid & (kTileY - 1);
-  const uint64_t clk = *clock + step_idx;
-  if (!PERSIST) {
-    const int tile = (xcd_tile(blockIdx.x, ngroups) << lg) + sub;
-    step_tile<S, R, BASIS, SAMPLE, ODD>(slots, prefix, nslots, tile < total_tiles ? tile : -1,
-                                        clk, sub, wave);
-  } else {
-    for (int gb = blockIdx.x; gb < ngroups; gb += gridDim.x) {
-      const int tile = (xcd_tile(gb, ngroups) << lg) + sub;
-      step_tile<S, R, BASIS, false, ODD>(slots, prefix, nslots,
-                                         tile < total_tiles ? tile : -1, clk, sub, wave);
-    }
-  }
-}
-
-__global__ void tick_kernel(uint64_t* clock, uint64_t n) { *clock += n; }
 
 // ---------------------------------------------------------------- state I/O
 // Write f (unshifted FP64, natural order, [9][ny][nx]) into storage at phase
@@ -795,75 +485,6 @@ __global__ void sk_accumulate_kernel(const typename Cplx<T>::type* __restrict__ 
   acc[2u * H + i] += cr * cr + ci * ci;
   acc[3u * H + i] += br * cr + bi * ci;  // Re(b conj c)
   acc[4u * H + i] += bi * cr - br * ci;  // Im(b conj c)
-}
-
-// ------------------------------------------------------------ launchers
-template <typename S, typename R, int BASIS>
-static hipError_t launch_step_t(bool sample, int odd, const SlotDesc* d_slots,
-                                const int* d_prefix, int nslots, int total_tiles,
-                                const uint64_t* d_clock, uint32_t step_idx, LaunchCfg cfg,
-                                hipStream_t st) {
-  if (total_tiles <= 0) return hipSuccess;
-  if (cfg.tiles_per_block != 1 && cfg.tiles_per_block != 2 && cfg.tiles_per_block != 4)
-    return hipErrorInvalidValue;
-  if (cfg.grid_blocks < 0 || cfg.grid_blocks % 8 != 0) return hipErrorInvalidValue;
-  const int tpb = std::min(cfg.tiles_per_block, sample ? max_tiles_per_block<R, true>()
-                                                       : max_tiles_per_block<R, false>());
-  const int ngroups = (total_tiles + tpb - 1) / tpb;
-  const int grid =
-      !sample && cfg.grid_blocks > 0 && cfg.grid_blocks < ngroups ? cfg.grid_blocks : ngroups;
-  const dim3 g(grid), b(kBlock * tpb);
-#define FLB_STEP(SMP, ODD, PER)                                                                 \
-  hipLaunchKernelGGL((step_kernel<S, R, BASIS, SMP, ODD, PER>), g, b, 0, st, d_slots, d_prefix, \
-                     nslots, total_tiles, d_clock, step_idx)
-  if (sample) {
-    if (odd) FLB_STEP(true, 1, false);
-    else FLB_STEP(true, 0, false);
-  } else if (grid < ngroups) {
-    if (odd) FLB_STEP(false, 1, true);
-    else FLB_STEP(false, 0, true);
-  } else {
-    if (odd) FLB_STEP(false, 1, false);
-    else FLB_STEP(false, 0, false);
-  }
-#undef FLB_STEP
-  return hipGetLastError();
-}
-
-template <typename S, typename R>
-static hipError_t launch_step_b(int basis, bool sample, int odd, const SlotDesc* a, const int* b,
-                                int c, int d, const uint64_t* e, uint32_t f, LaunchCfg cfg,
-                                hipStream_t g) {
-  switch (basis) {
-    case kBasisFnormLocal:
-      return launch_step_t<S, R, kBasisFnormLocal>(sample, odd, a, b, c, d, e, f, cfg, g);
-    case kBasisHermite:
-      return launch_step_t<S, R, kBasisHermite>(sample, odd, a, b, c, d, e, f, cfg, g);
-    case kBasisFnormLut:
-      return launch_step_t<S, R, kBasisFnormLut>(sample, odd, a, b, c, d, e, f, cfg, g);
-  }
-  return hipErrorInvalidValue;
-}
-
-// storage: 0 = FP64, 1 = FP32 shifted; compute: 0 = FP64, 1 = FP32; odd: the
-// streaming phase, which every slot of the launch shares (own time parity).
-hipError_t launch_step(int storage, int compute, int basis, bool sample, int odd,
-                       const SlotDesc* d_slots, const int* d_prefix, int nslots,
-                       int total_tiles, const uint64_t* d_clock, uint32_t step_idx,
-                       LaunchCfg cfg, hipStream_t st) {
-  if (storage == 0)
-    return launch_step_b<double, double>(basis, sample, odd, d_slots, d_prefix, nslots,
-                                         total_tiles, d_clock, step_idx, cfg, st);
-  if (compute == 0)
-    return launch_step_b<float, double>(basis, sample, odd, d_slots, d_prefix, nslots,
-                                        total_tiles, d_clock, step_idx, cfg, st);
-  return launch_step_b<float, float>(basis, sample, odd, d_slots, d_prefix, nslots, total_tiles,
-                                     d_clock, step_idx, cfg, st);
-}
-
-hipError_t launch_tick(uint64_t* d_clock, uint64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, d_clock, n);
-  return hipGetLastError();
 }
 
 static dim3 row_grid(int nx, int rows) { return dim3((nx + 255) / 256, rows); }

@@ -43,6 +43,11 @@ struct SlotDesc {
 }  // namespace flb
 
 namespace flb {
+// Complex value of a real type.
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+
 // Launch shape of the batched step: tiles per workgroup (1, 2 or 4) and the
 // grid (0: one workgroup per tile group; > 0, a multiple of 8: a persistent
 // grid of that many workgroups striding over the tile groups).  Every shape
