@@ -94,6 +94,7 @@ typedef struct {
   double cov_m_hermite[81];   /* m C m^T, Hermite rows of eq. (A3)                */
   double se_cov_f[81];        /* standard errors from the time blocks (NaN if < 2)*/
   double se_cov_m[81];        /* same for cov_m_fnorm_u0                          */
+  double se_cov_m_hermite[81];  /* same for cov_m_hermite                         */
 } flb_cov;
 
 typedef struct flb_lattice flb_lattice;
@@ -195,6 +196,8 @@ int flb_ensemble_step(flb_ensemble* E, uint64_t nsteps);
 int flb_ensemble_sync(flb_ensemble* E);
 int flb_ensemble_read_populations(flb_ensemble* E, int32_t i, double* f);
 int flb_ensemble_read_covariance(flb_ensemble* E, int32_t i, flb_cov* out);
+/* Restart the correlator sums of every replica (as flb_lattice_reset_stats). */
+int flb_ensemble_reset_stats(flb_ensemble* E);
 uint64_t flb_ensemble_time(flb_ensemble* E);
 /* Device time of the step launches (graph replays count one launch per step). */
 int flb_ensemble_profile(flb_ensemble* E, int32_t on);

@@ -45,6 +45,7 @@ class Cov(C.Structure):
         ("mean_df", C.c_double * 9), ("cov_f", C.c_double * 81),
         ("cov_m_fnorm_u0", C.c_double * 81), ("cov_m_hermite", C.c_double * 81),
         ("se_cov_f", C.c_double * 81), ("se_cov_m", C.c_double * 81),
+        ("se_cov_m_hermite", C.c_double * 81),
     ]
 
 
@@ -106,6 +107,7 @@ _SIGS = {
     "flb_ensemble_sync": [C.c_void_p],
     "flb_ensemble_read_populations": [C.c_void_p, C.c_int32, C.POINTER(C.c_double)],
     "flb_ensemble_read_covariance": [C.c_void_p, C.c_int32, C.POINTER(Cov)],
+    "flb_ensemble_reset_stats": [C.c_void_p],
     "flb_ensemble_profile": [C.c_void_p, C.c_int32],
     "flb_ensemble_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
     "flb_lattice_autotune": [C.c_void_p, C.c_int32, C.POINTER(LaunchConfig), C.c_int32,
@@ -194,7 +196,8 @@ def make_params(nx, ny, rho0=1.0, ux0=0.0, uy0=0.0, kT=0.0, tau=(1.0,) * 6, seed
 def _cov_dict(c: Cov) -> dict:
     out = {"nsamples": int(c.nsamples), "nblocks": int(c.nblocks),
            "mean_df": np.array(c.mean_df[:])}
-    for k in ("cov_f", "cov_m_fnorm_u0", "cov_m_hermite", "se_cov_f", "se_cov_m"):
+    for k in ("cov_f", "cov_m_fnorm_u0", "cov_m_hermite", "se_cov_f", "se_cov_m",
+              "se_cov_m_hermite"):
         out[k] = np.array(getattr(c, k)[:]).reshape(9, 9)
     return out
 
@@ -384,6 +387,9 @@ class Ensemble(_Tunable):
         c = Cov()
         _check(load().flb_ensemble_read_covariance(self.h, i, C.byref(c)), "ensemble_cov")
         return _cov_dict(c)
+
+    def reset_stats(self):
+        _check(load().flb_ensemble_reset_stats(self.h), "ensemble_reset_stats")
 
     def profile(self, on: bool = True):
         _check(load().flb_ensemble_profile(self.h, 1 if on else 0), "profile")

@@ -795,6 +795,10 @@ int flb_ensemble_read_covariance(flb_ensemble* E, int32_t i, flb_cov* out) {
   if (i < 0 || i >= (int)E->g.P.size() || !out) return flb::set_error(FLB_E_ARG, "bad replica");
   return E->g.read_covariance(i, out);
 }
+int flb_ensemble_reset_stats(flb_ensemble* E) {
+  NEED(E);
+  return E->g.reset_stats();
+}
 uint64_t flb_ensemble_time(flb_ensemble* E) { return E ? E->g.t : 0; }
 int flb_ensemble_profile(flb_ensemble* E, int32_t on) {
   NEED(E);

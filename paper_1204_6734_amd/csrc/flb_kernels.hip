@@ -108,8 +108,8 @@ __global__ void init_kernel(S* pop, const double* __restrict__ rho, const double
   double n9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (mu > 0.0) {
     double a[6], b[6];
-    site_gaussians<double>(k0, k1, site, 0, 0x80000000u, a);
-    site_gaussians<double>(k0, k1, site, 1, 0x80000000u, b);
+    site_gaussians<double>(k0, k1, site, 0, 0x80000000u, 1.0, a);
+    site_gaussians<double>(k0, k1, site, 1, 0x80000000u, 1.0, b);
     for (int i = 0; i < 6; ++i) n9[i] = a[i];
     for (int i = 0; i < 3; ++i) n9[6 + i] = b[i];
   }

@@ -267,28 +267,35 @@ int finish_covariance(const Stats& S, const std::vector<double>& rec, const doub
   transform(mt0, out->cov_f, out->cov_m_fnorm_u0);
   transform(m, out->cov_f, out->cov_m_hermite);
   if (S.nb >= 2) {
-    double sf[81] = {0}, sf2[81] = {0}, sm[81] = {0}, sm2[81] = {0};
+    double sf[81] = {0}, sf2[81] = {0}, sm[81] = {0}, sm2[81] = {0}, sh[81] = {0}, sh2[81] = {0};
     for (uint64_t b = 0; b < S.nb; ++b) {
       const double nbk = (double)S.block_samples(b) * (double)sites;
-      double Cb[81], Mb[81];
+      double Cb[81], Mb[81], Hb[81];
       cov_from(&rec[b * kNStat], nbk, Cb);
       transform(mt0, Cb, Mb);
+      transform(m, Cb, Hb);
       for (int k = 0; k < 81; ++k) {
         sf[k] += Cb[k];
         sf2[k] += Cb[k] * Cb[k];
         sm[k] += Mb[k];
         sm2[k] += Mb[k] * Mb[k];
+        sh[k] += Hb[k];
+        sh2[k] += Hb[k] * Hb[k];
       }
     }
     const double nb = (double)S.nb;
+    auto se = [nb](double s1, double s2) {
+      const double v = (s2 - s1 * s1 / nb) / (nb - 1);
+      return std::sqrt(v > 0 ? v / nb : 0.0);
+    };
     for (int k = 0; k < 81; ++k) {
-      const double vf = (sf2[k] - sf[k] * sf[k] / nb) / (nb - 1);
-      const double vm = (sm2[k] - sm[k] * sm[k] / nb) / (nb - 1);
-      out->se_cov_f[k] = std::sqrt(vf > 0 ? vf / nb : 0.0);
-      out->se_cov_m[k] = std::sqrt(vm > 0 ? vm / nb : 0.0);
+      out->se_cov_f[k] = se(sf[k], sf2[k]);
+      out->se_cov_m[k] = se(sm[k], sm2[k]);
+      out->se_cov_m_hermite[k] = se(sh[k], sh2[k]);
     }
   } else {
-    for (int k = 0; k < 81; ++k) out->se_cov_f[k] = out->se_cov_m[k] = NAN;
+    for (int k = 0; k < 81; ++k)
+      out->se_cov_f[k] = out->se_cov_m[k] = out->se_cov_m_hermite[k] = NAN;
   }
   return FLB_OK;
 }

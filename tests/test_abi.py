@@ -39,7 +39,7 @@ def test_struct_layouts():
     # flb_params: 2 int32, 4 doubles, 6 doubles, uint64, 6 int32
     assert C.sizeof(F.Params) == 8 + 8 * 4 + 8 * 6 + 8 + 4 * 6
     assert F.Params.tau.offset == 40 and F.Params.seed.offset == 88
-    assert C.sizeof(F.Cov) == 16 + 8 * (9 + 81 * 5)
+    assert C.sizeof(F.Cov) == 16 + 8 * (9 + 81 * 6)
     assert F.Result.cov.offset == 56
 
 
