@@ -142,7 +142,7 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
     hdesc[s].err = d_err + s;
     hdesc[s].err_step = d_err_step + s;
     hdesc[s].t0 = 0;
-    hdesc[s].tend = ~0ull;
+    hdesc[s].tend = 0x7FFFFFFFFFFFFFFFull;  // never
     fnorm_rows(ps[s].ux0, ps[s].uy0, mt0[s].data());
     stats[s].reset(ps[s].block_steps);
   }

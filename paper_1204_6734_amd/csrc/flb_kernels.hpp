@@ -26,8 +26,9 @@ struct SlotDesc {
   int* err;             // error bits (atomicOr)
   unsigned long long* err_step;  // first failing step (atomicMin)
   int nx, ny, tiles_x, ntiles;
+  uint32_t tx_magic, tx_shift;  // local tile t: row of tiles = (t * tx_magic) >> tx_shift
   uint64_t t0;          // own time = t0 + clock (mod 2^64)
-  uint64_t tend;        // no update once own time >= tend
+  uint64_t tend;        // no update once own time >= tend (tend < 2^63)
   uint32_t k0, k1;      // Philox key = seed
   int sample_every;     // 0: never
   int sk_every;         // 0: never

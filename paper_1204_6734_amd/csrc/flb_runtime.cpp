@@ -151,6 +151,18 @@ void fill_slot(const flb_params* p, SlotDesc* d) {
   d->ny = p->ny;
   d->tiles_x = (p->nx + kTileX - 1) / kTileX;
   d->ntiles = d->tiles_x * ((p->ny + kTileY - 1) / kTileY);
+  // t / tiles_x as a multiply-shift (Granlund-Montgomery, round-up
+  // variant): m = ceil(2^k / d) with k = 32 + floor(log2 d) (31 + log2 d for
+  // a power of two, where the division is exact) fits 32 bits, and its error
+  // e = m d - 2^k < d keeps floor(t m / 2^k) = floor(t / d) for all t < 2^31
+  {
+    const uint64_t dv = (uint64_t)d->tiles_x;
+    int lg = 0;
+    while ((2ull << lg) <= dv) ++lg;  // floor(log2 d)
+    const int k = (dv & (dv - 1)) == 0 ? 31 + lg : 32 + lg;
+    d->tx_magic = (uint32_t)(((1ull << k) + dv - 1) / dv);
+    d->tx_shift = (uint32_t)k;
+  }
   d->k0 = (uint32_t)p->seed;
   d->k1 = (uint32_t)(p->seed >> 32);
   d->sample_every = p->sample_every;

@@ -416,6 +416,7 @@ int flb_server_submit(flb_server* S, const flb_request* r, uint64_t* id) {
   int rc = check_params(&q.p);
   if (rc != FLB_OK) return rc;
   if (q.nsteps == 0) return set_error(FLB_E_ARG, "request needs at least one step");
+  if (q.nsteps >= (1ull << 62)) return set_error(FLB_E_ARG, "request of 2^62 steps or more");
   if (request_bytes_of(q.p, S->cfg.precision) > S->cfg.mem_budget_bytes)
     return set_error(FLB_E_ADMISSION, "request footprint exceeds the memory budget");
   {

@@ -156,33 +156,45 @@ __device__ __forceinline__ void sample_correlators(const R h[9], bool active, bo
 }
 
 // Byte offsets (within their planes) of the nine populations a site reads
-// in phase ODD, with the plane each one lives in.  Even phase: plane i at
-// the site itself.  Odd phase: plane opp(i) at x - v_i.  After the
-// collision the value of direction kOpp[i] goes back to the same place.
-// Rows are wave-uniform (one wavefront = 64 sites of one row), so only the
-// x wrap is per lane.
+// in phase ODD, split into a per-lane column part (voff) and a wave-uniform
+// row part (soff, passed in the buffer instruction's scalar offset, so no
+// per-lane add is needed).  Even phase: plane i at the site itself.  Odd
+// phase: plane opp(i) at x - v_i.  After the collision the value of
+// direction kOpp[i] goes back to the same place.  Rows are wave-uniform
+// (one wavefront = 64 sites of one row), so only the x wrap is per lane, and
+// only wavefronts at the two ends of a row can wrap.
 template <typename S, int ODD>
-__device__ __forceinline__ void site_offsets(int x, int y, int nx, int ny, uint32_t off[9]) {
+__device__ __forceinline__ void site_offsets(int x, int y, int nx, int ny, bool x_edge,
+                                             uint32_t voff[9], uint32_t soff[9]) {
   constexpr uint32_t E = sizeof(S);
   const uint32_t rc = (uint32_t)y * nx * E;
   const uint32_t xc = (uint32_t)x * E;
   if (!ODD) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) off[i] = rc + xc;
+    for (int i = 0; i < 9; ++i) {
+      voff[i] = xc;
+      soff[i] = rc;
+    }
   } else {
     const uint32_t rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx * E;
     const uint32_t rp = (uint32_t)(y == ny - 1 ? 0 : y + 1) * nx * E;
-    const uint32_t xm = x == 0 ? (uint32_t)(nx - 1) * E : xc - E;
-    const uint32_t xp = x == nx - 1 ? 0u : xc + E;
-    off[0] = rc + xc;
-    off[1] = rc + xm;  // v=( 1, 0) from (x-1, y)
-    off[2] = rm + xc;  // v=( 0, 1) from (x, y-1)
-    off[3] = rc + xp;  // v=(-1, 0) from (x+1, y)
-    off[4] = rp + xc;  // v=( 0,-1) from (x, y+1)
-    off[5] = rm + xm;  // v=( 1, 1) from (x-1, y-1)
-    off[6] = rm + xp;  // v=(-1, 1) from (x+1, y-1)
-    off[7] = rp + xp;  // v=(-1,-1) from (x+1, y+1)
-    off[8] = rp + xm;  // v=( 1,-1) from (x-1, y+1)
+    uint32_t xm = xc - E, xp = xc + E;
+    if (x_edge) {
+      // a wave-uniform branch: the empty volatile asm keeps the compiler
+      // from turning the wrap into selects that every wavefront would run
+      asm volatile("" : "+v"(xm), "+v"(xp));
+      xm = x == 0 ? (uint32_t)(nx - 1) * E : xm;
+      xp = x == nx - 1 ? 0u : xp;
+    }
+    voff[0] = xc; soff[0] = rc;
+    voff[1] = xm; soff[1] = rc;  // v=( 1, 0) from (x-1, y)
+    voff[2] = xc; soff[2] = rm;  // v=( 0, 1) from (x, y-1)
+    voff[3] = xp; soff[3] = rc;  // v=(-1, 0) from (x+1, y)
+    voff[4] = xc; soff[4] = rp;  // v=( 0,-1) from (x, y+1)
+    voff[5] = xm; soff[5] = rm;  // v=( 1, 1) from (x-1, y-1)
+    voff[6] = xp; soff[6] = rm;  // v=(-1, 1) from (x+1, y-1)
+    voff[7] = xp; soff[7] = rp;  // v=(-1,-1) from (x+1, y+1)
+    voff[8] = xm; soff[8] = rp;  // v=( 1,-1) from (x-1, y+1)
   }
 }
 
@@ -196,18 +208,22 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(void* pop, uint32_t
   return __builtin_amdgcn_make_buffer_rsrc(base, 0, N * (uint32_t)sizeof(S), 0x00020000);
 }
 
-__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, float*) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, double*) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                           uint32_t soff, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
-__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                          float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
 }
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                          double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
 // One tile (or none: tile < 0) of the batched step.  A tile of a slot whose
@@ -221,23 +237,29 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   const int s = have ? find_slot(prefix, nslots, tile) : 0;
   const SlotDesc& sd = slots[s];
   const uint64_t t = sd.t0 + clk;
-  const bool live = have && t < sd.tend;
+  // t < tend, as the sign of tend - t (both below 2^63; the scalar unit has
+  // no 64-bit ordered compare)
+  const uint64_t rem = sd.tend - t;
+  const bool live = have && (int32_t)(uint32_t)(rem >> 32) >= 0 && rem != 0;
   if (!SAMPLE && !live) return;
   const int lt = tile - prefix[s];
   const int nx = sd.nx, ny = sd.ny;
-  const int ty = lt / sd.tiles_x, tx = lt - ty * sd.tiles_x;
+  // lt / tiles_x by multiply-shift on the scalar unit
+  const int ty = (int)(((uint64_t)(uint32_t)lt * sd.tx_magic) >> sd.tx_shift);
+  const int tx = lt - ty * sd.tiles_x;
   const int x = tx * kTileX + (threadIdx.x & (kTileX - 1));
   const int y = ty * kTileY + wave;
   const bool active = live && (x < nx) && (y < ny);
   const uint32_t N = (uint32_t)nx * (uint32_t)ny;
 
-  uint32_t off[9];
+  uint32_t voff[9], soff[9];
   R h[9];
   if (active) {
-    site_offsets<S, ODD>(x, y, nx, ny, off);
+    site_offsets<S, ODD>(x, y, nx, ny, tx == 0 || tx == sd.tiles_x - 1, voff, soff);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      h[i] = (R)buf_load(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), off[i], (S*)nullptr);
+      h[i] = (R)buf_load(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), voff[i], soff[i],
+                         (S*)nullptr);
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) h[i] = R(0);
@@ -274,7 +296,7 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    buf_store(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), off[i], (S)h[kOpp[i]]);
+    buf_store(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), voff[i], soff[i], (S)h[kOpp[i]]);
 }
 
 // Tiles per workgroup a step variant accepts: the sampling variants and the
