@@ -80,14 +80,19 @@ def cpu_baseline(seconds: float = 12.0) -> dict:
                       f"FP64 C oracle single-threaded, {dt:.1f} s"}
 
 
-def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 100):
+def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 100,
+              launch=None):
     from paper_1204_6734_amd import inputs as I
     stream = torch.cuda.current_stream()
     p = F.make_params(nx, nx, precision=F.FP32_SHIFTED, rho0=1.0, ux0=0.1, kT=1e-4, seed=1,
                       init=F.INIT_FIELDS, sk_every=every)
     L = F.Lattice(p, stream=stream)
     L.set_fields(*I.shear_wave_fields(nx, nx, ux0=0.1, amp=1e-3))
-    tune = L.autotune(reps=3)  # trial steps run on a copy of the state
+    if launch is None:
+        tune = L.autotune(reps=3)  # trial steps run on a copy of the state
+    else:
+        L.set_launch(*launch)
+        tune = "fixed by --launch"
 
     chunk = every if every > 0 else 100
 
@@ -246,6 +251,9 @@ def main():
     ap.add_argument("--sk-every", type=int, default=100,
                     help="structure-factor and mode-log interval of the large workload (0: off)")
     ap.add_argument("--rate", type=float, default=50.0, help="serving arrival rate (1/s)")
+    ap.add_argument("--launch", default=None,
+                    help="TILES,GRID: fix the step launch shape instead of autotuning "
+                         "(profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -272,7 +280,9 @@ def main():
         r = run_serving(F, torch, nreq=args.requests or 400, rate=args.rate)
         print(json.dumps({"workload": "serving, Poisson 50/s", **r}), flush=True)
         return
-    r = run_large(F, torch, args.steps, args.warmup, nx=args.nx, every=args.sk_every)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    r = run_large(F, torch, args.steps, args.warmup, nx=args.nx, every=args.sk_every,
+                  launch=launch)
     mlups = r["sites"] * args.steps / r["dt"] / 1e6
     bps = BYTES_PER_SITE[r["dtype"]]
     achieved = bps * r["sites"] / (r["kernel_ms"] * 1e-3) / 1e9
