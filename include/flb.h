@@ -140,6 +140,10 @@ int flb_lattice_sync(flb_lattice* L);
 /* Current populations, unshifted FP64, into caller-owned host [9][ny][nx].
  * Synchronises; returns a pending device error instead of data. */
 int flb_lattice_read_populations(flb_lattice* L, double* f);
+/* Rows [y0, y0 + nrows) only, into host [9][nrows][nx] (same conventions);
+ * for lattices too large to copy out whole.  FLB_E_ARG for rows outside
+ * 0..ny. */
+int flb_lattice_read_rows(flb_lattice* L, int32_t y0, int32_t nrows, double* f);
 /* Moments per site into host [9][ny][nx]: FLB_AT_LOCAL = f-norm at the local
  * velocity (eq. (31): rho, 0, 0, then the non-equilibrium M~^{3..8}),
  * FLB_AT_U0 = f-norm at (rho0, u0) (the measurement basis of Sec. IV, after

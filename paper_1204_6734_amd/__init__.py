@@ -91,6 +91,7 @@ _SIGS = {
     "flb_lattice_step": [C.c_void_p, C.c_uint64],
     "flb_lattice_sync": [C.c_void_p],
     "flb_lattice_read_populations": [C.c_void_p, C.POINTER(C.c_double)],
+    "flb_lattice_read_rows": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)],
     "flb_lattice_read_moments": [C.c_void_p, C.c_int32, C.POINTER(C.c_double)],
     "flb_lattice_read_covariance": [C.c_void_p, C.POINTER(Cov)],
     "flb_lattice_read_structure_factor": [C.c_void_p, C.c_int32, C.POINTER(C.c_double)],
@@ -295,6 +296,12 @@ class Lattice(_Tunable):
     def populations(self) -> np.ndarray:
         f = np.empty((9, self.p.ny, self.p.nx))
         _check(load().flb_lattice_read_populations(self.h, _dp(f)), "read_populations")
+        return f
+
+    def rows(self, y0: int, nrows: int) -> np.ndarray:
+        """Populations of rows [y0, y0 + nrows), [9][nrows][nx]."""
+        f = np.empty((9, nrows, self.p.nx))
+        _check(load().flb_lattice_read_rows(self.h, y0, nrows, _dp(f)), "read_rows")
         return f
 
     def moments(self, at: int = AT_U0) -> np.ndarray:

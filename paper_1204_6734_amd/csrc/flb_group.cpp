@@ -384,17 +384,24 @@ int Group::sync() {
 }
 
 int Group::read_populations(int s, double* f) {
+  return read_rows(s, 0, P[s].ny, f);
+}
+
+// Rows [y0, y0 + nrows) of slot s, unshifted FP64, [9][nrows][nx].
+int Group::read_rows(int s, int y0, int nrows, double* f) {
   int rc = sync();
   if (rc != FLB_OK) return rc;
   const flb_params& p = P[s];
-  const size_t N = (size_t)p.nx * p.ny;
-  for (int y0 = 0; y0 < p.ny; y0 += band_rows) {
-    const int rows = std::min(band_rows, p.ny - y0);
+  if (y0 < 0 || nrows < 0 || y0 + nrows > p.ny)
+    return set_error(FLB_E_ARG, "rows [%d, %d) outside 0..%d", y0, y0 + nrows, p.ny);
+  const size_t N = (size_t)p.nx * nrows;
+  for (int b0 = y0; b0 < y0 + nrows; b0 += band_rows) {
+    const int rows = std::min(band_rows, y0 + nrows - b0);
     HIPC(launch_read_state(storage, pop[s], d_io, p.nx, p.ny, (int)(t & 1), slot_shift(hdesc[s]),
-                           y0, rows, st));
+                           b0, rows, st));
     const size_t B = (size_t)rows * p.nx;
     for (int i = 0; i < 9; ++i)
-      HIPC(hipMemcpyAsync(f + i * N + (size_t)y0 * p.nx, d_io + i * B, B * sizeof(double),
+      HIPC(hipMemcpyAsync(f + i * N + (size_t)(b0 - y0) * p.nx, d_io + i * B, B * sizeof(double),
                           hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
   }
@@ -707,6 +714,11 @@ int flb_lattice_read_populations(flb_lattice* L, double* f) {
   NEED(L);
   if (!f) return flb::set_error(FLB_E_ARG, "null output");
   return L->g.read_populations(0, f);
+}
+int flb_lattice_read_rows(flb_lattice* L, int32_t y0, int32_t nrows, double* f) {
+  NEED(L);
+  if (!f) return flb::set_error(FLB_E_ARG, "null output");
+  return L->g.read_rows(0, y0, nrows, f);
 }
 int flb_lattice_read_moments(flb_lattice* L, int32_t at, double* m) {
   NEED(L);

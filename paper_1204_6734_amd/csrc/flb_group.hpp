@@ -79,6 +79,7 @@ struct Group {
   int step(uint64_t nsteps);
   int sync();
   int read_populations(int s, double* f);
+  int read_rows(int s, int y0, int nrows, double* f);
   int set_populations(int s, const double* f, uint64_t tnew);
   int set_fields(int s, const double* rho, const double* ux, const double* uy);
   int read_moments(int s, int at, double* m);

@@ -122,3 +122,35 @@ def test_16384_row_fp32_structure_factor_matches_oracle(flb):
     scale = np.abs(o.structure_factor(0)).max()
     for w in range(5):
         assert np.abs(g.structure_factor(w) - o.structure_factor(w)).max() <= 2e-5 * scale, w
+
+
+def test_16384_fp32_sampled_sites_by_rows(flb):
+    """The largest lattice of the tests: 16384^2 FP32-shifted (9.7 GB of
+    populations, 1 GiB planes, 4x the benchmark), thermal start.  Sampled
+    sites (corners, edges, random) after an odd and an even step against the
+    oracle's collision of their neighbours, reading only the rows needed."""
+    nx = ny = 16384
+    kw = dict(ux0=0.1, kT=1e-4, seed=3, tau=I.mixed_taus(2))
+    L = flb.Lattice(flb.make_params(nx, ny, precision=flb.FP32_SHIFTED, init=flb.INIT_THERMAL,
+                                    **kw))
+    po = O.make_params(nx, ny, **kw)
+    rng = np.random.default_rng(4)
+    sites = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1), (8191, 8192), (64, ny - 1)]
+    sites += [(int(a), int(b)) for a, b in zip(rng.integers(0, nx, 20), rng.integers(0, ny, 20))]
+    L.step(3)
+    for _ in range(2):  # odd phase, then even phase
+        t = L.t
+        need = sorted({(y + d) % ny for (_, y) in sites for d in (-1, 0, 1)})
+        before = {yy: L.rows(yy, 1)[:, 0, :] for yy in need}
+        L.step(1)
+        err = 0.0
+        for (x, y) in sites:
+            got = L.rows(y, 1)[:, 0, x]
+            want = np.empty(9)
+            for i in range(9):
+                xs, ys = (x - VX[i]) % nx, (y - VY[i]) % ny
+                fo = O.collide(po, before[ys][:, xs], site=ys * nx + xs, step=t)
+                want[i] = fo[i]
+            err = max(err, np.abs(got - want).max())
+        print(f"16384^2 step {t}: max |f - oracle| = {err:.2e}")
+        assert err <= 2e-7, (t, err)
