@@ -273,7 +273,7 @@ typedef struct {
 
 typedef struct {
   flb_params p;            /* p.precision / p.basis are taken from the config      */
-  uint64_t nsteps;
+  uint64_t nsteps;         /* 1 .. 2^62 - 1 (FLB_E_ARG otherwise)                  */
   uint64_t tag;            /* caller's id, returned with the result                */
 } flb_request;
 
