@@ -136,11 +136,27 @@ __device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint32_
 }
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+// FP64 1/sqrt(x) and 1/x: the hardware estimates refined by Newton-Raphson
+// (three steps for the square root, each at least doubling the correct bits
+// of the estimate; two for the reciprocal), to within a few ulp of the
+// correctly rounded values at a fraction of the cost of sqrt and divide.
+// Arguments are positive and finite here (pivots and densities).
+__device__ __forceinline__ double rsqrt_t(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r = fma(r, fma(-hx * r, r, 0.5), r);
+  return r;
+}
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
-__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+__device__ __forceinline__ double rcp_t(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
 
 // Per-lattice constants of the collision, in the compute type.  The stored
 // populations are h_i = f_i - f_i^0(rho0, u0): everything below works with
