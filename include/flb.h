@@ -189,8 +189,10 @@ const char* flb_last_error(void);
 /* ------------------------------------------------------------- ensembles
  * n replicas of one lattice shape (same nx, ny, precision, basis), each with
  * its own rho0, u0, kT, tau, seed and sampling, advanced by one batched
- * kernel launch per step; chunks of steps are replayed from a captured
- * hipGraph.  Replica results are bit-identical to running each alone. */
+ * kernel launch per step (two when some FP32 replicas have |u0| > 0.25 and
+ * need the FP64 collision: those form their own launch); chunks of steps are
+ * replayed from a captured hipGraph.  Replica results are bit-identical to
+ * running each alone. */
 typedef struct flb_ensemble flb_ensemble;
 int flb_ensemble_create(const flb_params* per_replica, int32_t n, void* hip_stream,
                         flb_ensemble** out);

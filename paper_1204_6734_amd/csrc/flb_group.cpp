@@ -30,7 +30,7 @@ static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 void Group::layout(Arena& a) {
   const int n = (int)P.size();
   d_slots = a.take<SlotDesc>(n);
-  d_prefix = a.take<int>(n + 1);
+  d_prefix = a.take<int>(n + 2);
   d_clock = a.take<uint64_t>(1);
   d_err = a.take<int>(n);
   d_err_step = a.take<unsigned long long>(n);
@@ -84,6 +84,20 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
   basis = ps[0].basis;
   compute = 1;
   for (int s = 0; s < n; ++s) compute = std::min(compute, compute_precision(&ps[s]));
+  // launch classes: FP32-compute members first, then FP64-compute members
+  corder.clear();
+  nclass = 0;
+  for (int cc : {1, 0}) {
+    const int first = (int)corder.size();
+    for (int s = 0; s < n; ++s)
+      if (compute_precision(&ps[s]) == cc) corder.push_back(s);
+    if ((int)corder.size() > first) {
+      ccompute[nclass] = cc;
+      cfirst[nclass] = first;
+      ccount[nclass] = (int)corder.size() - first;
+      ++nclass;
+    }
+  }
   hdesc.assign(n, SlotDesc{});
   prefix.assign(n + 1, 0);
   for (int s = 0; s < n; ++s) {
@@ -146,8 +160,24 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
     fnorm_rows(ps[s].ux0, ps[s].uy0, mt0[s].data());
     stats[s].reset(ps[s].block_steps);
   }
-  HIPC(hipMemcpyAsync(d_slots, hdesc.data(), n * sizeof(SlotDesc), hipMemcpyHostToDevice, st));
-  HIPC(hipMemcpyAsync(d_prefix, prefix.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  {
+    std::vector<SlotDesc> dev_desc(n);
+    std::vector<int> dev_prefix;
+    for (int c = 0; c < nclass; ++c) {
+      int acc = 0;
+      dev_prefix.push_back(0);
+      for (int j = 0; j < ccount[c]; ++j) {
+        const int s = corder[cfirst[c] + j];
+        dev_desc[cfirst[c] + j] = hdesc[s];
+        acc += hdesc[s].ntiles;
+        dev_prefix.push_back(acc);
+      }
+      ctiles[c] = acc;
+    }
+    HIPC(hipMemcpy(d_slots, dev_desc.data(), n * sizeof(SlotDesc), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(d_prefix, dev_prefix.data(), dev_prefix.size() * sizeof(int),
+                   hipMemcpyHostToDevice));
+  }
   HIPC(hipMemsetAsync(d_clock, 0, sizeof(uint64_t), st));
   HIPC(hipMemsetAsync(d_err, 0, n * sizeof(int), st));
   HIPC(hipMemsetAsync(d_err_step, 0xFF, n * sizeof(unsigned long long), st));
@@ -231,21 +261,30 @@ int Group::after_step(uint64_t tt) {
   return FLB_OK;
 }
 
+// The step launches of one step: one per compute class.
+hipError_t Group::launch_classes(uint32_t k, bool sample, int odd, LaunchCfg c) {
+  for (int i = 0; i < nclass; ++i) {
+    const hipError_t e = launch_step(storage, ccompute[i], basis, sample, odd, d_slots + cfirst[i],
+                                     d_prefix + cfirst[i] + i, ccount[i], ctiles[i], d_clock, k,
+                                     c, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 int Group::launch_one(uint32_t k, bool sample, int odd) {
   if (profiling) {
     std::pair<hipEvent_t, hipEvent_t> ev;
     HIPC(hipEventCreate(&ev.first));
     HIPC(hipEventCreate(&ev.second));
     HIPC(hipEventRecord(ev.first, st));
-    HIPC(launch_step(storage, compute, basis, sample, odd, d_slots, d_prefix, (int)P.size(),
-                     total_tiles, d_clock, k, launch, st));
+    HIPC(launch_classes(k, sample, odd, launch));
     HIPC(hipEventRecord(ev.second, st));
     events.push_back(ev);
     prof_launches += 1;
     return FLB_OK;
   }
-  HIPC(launch_step(storage, compute, basis, sample, odd, d_slots, d_prefix, (int)P.size(),
-                   total_tiles, d_clock, k, launch, st));
+  HIPC(launch_classes(k, sample, odd, launch));
   return FLB_OK;
 }
 
@@ -286,8 +325,7 @@ int Group::capture_graph() {
     // interval
     bool sample = false;
     for (auto& p : P) sample |= p.sample_every > 0 && k % p.sample_every == 0;
-    hipError_t e = launch_step(storage, compute, basis, sample, k & 1, d_slots, d_prefix,
-                               (int)P.size(), total_tiles, d_clock, (uint32_t)k, launch, st);
+    hipError_t e = launch_classes((uint32_t)k, sample, k & 1, launch);
     if (e != hipSuccess) {
       hipGraph_t g;
       (void)hipStreamEndCapture(st, &g);

@@ -20,6 +20,15 @@ struct Group {
   std::vector<SlotDesc> hdesc;
   std::vector<int> prefix;
   int storage = 1, compute = 1, basis = 0, total_tiles = 0;
+  // Members whose background speed needs the FP64 collision (FP32 storage,
+  // |u0| > 0.25) form their own launch class, so that every member computes
+  // exactly as it would alone.  Class c: compute precision ccompute[c], the
+  // device descriptors d_slots + cfirst[c] (members in class order), tile
+  // prefix sums d_prefix + cfirst[c] + c, ccount[c] members and ctiles[c]
+  // tiles.
+  int nclass = 1;
+  int ccompute[2] = {1, 0}, cfirst[2] = {0, 0}, ccount[2] = {0, 0}, ctiles[2] = {0, 0};
+  std::vector<int> corder;  // device position -> member
   hipStream_t st = nullptr;
   bool own_stream = false, own_mem = false;
   void* dev = nullptr;
@@ -73,6 +82,7 @@ struct Group {
   bool sk_due(int s, uint64_t tt) const;
   int after_step(uint64_t tt);
   int launch_one(uint32_t k, bool sample, int odd);
+  hipError_t launch_classes(uint32_t k, bool sample, int odd, LaunchCfg c);
   bool graph_friendly() const;
   uint64_t steps_to_close() const;
   int capture_graph();

@@ -144,8 +144,7 @@ int Group::autotune(int reps, flb_launch_config* results, int max_results, int* 
   // to the phase it started in
   auto pair = [&](const LaunchCfg& c) -> hipError_t {
     for (uint32_t k = 0; k < 2; ++k) {
-      hipError_t r = launch_step(storage, compute, basis, false, (int)((t + k) & 1), d_slots,
-                                 d_prefix, n, total_tiles, d_clock, k, c, st);
+      hipError_t r = launch_classes(k, false, (int)((t + k) & 1), c);
       if (r != hipSuccess) return r;
     }
     return hipSuccess;

@@ -71,6 +71,21 @@ def test_fp32_shifted_moments_match_fp64_oracle(flb, ux0):
     assert worst <= 1e-5, worst
 
 
+@pytest.mark.parametrize("basis", ["fnorm", "lut"])
+def test_fp32_storage_fp64_compute_matches_oracle(flb, basis):
+    """|u0| above 0.25: FP32-shifted storage with the collision computed in
+    FP64 (the large-velocity path), against the oracle after 1000 steps."""
+    b = {"fnorm": flb.BASIS_FNORM_LOCAL, "lut": flb.BASIS_FNORM_LUT}[basis]
+    nx, ny = 100, 30
+    kw = dict(ux0=0.3, uy0=0.1, kT=1e-4, tau=TAUS, seed=12)
+    g, o = both(flb, nx, ny, flb.FP32_SHIFTED, basis=b, **kw)
+    g.step(1000)
+    o.step(1000)
+    mg, mo = g.moments(flb.AT_U0), o.moments(flb.AT_U0)
+    worst = max(np.abs(mg[a] - mo[a]).max() / np.abs(mo[a]).max() for a in range(9))
+    assert worst <= 1e-5, worst
+
+
 def test_covariance_sums_match_oracle(flb):
     kw = dict(ux0=0.1, kT=1e-4, tau=TAUS, seed=5, sample_every=1, block_steps=50)
     g, o = both(flb, 40, 24, flb.FP64, **kw)

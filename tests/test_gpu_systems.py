@@ -163,3 +163,39 @@ def test_ensemble_graph_with_sampling_interval(flb):
         assert ce["nsamples"] == cl["nsamples"] == 25 * 64 * 24
         assert ce["nblocks"] == cl["nblocks"] == 3
         np.testing.assert_array_equal(ce["cov_f"], cl["cov_f"])
+
+
+def test_server_mixed_compute_classes_alone_equals_in_mix(flb):
+    """Requests above |u0| = 0.25 run in the FP64-compute class, the others in
+    FP32; both classes advance together and each result equals its solo run
+    and the single-lattice run of the same parameters."""
+    reqs = []
+    for k, (side, n, ux) in enumerate([(48, 90, 0.3), (64, 60, 0.1), (40, 120, 0.28),
+                                       (56, 70, 0.0)]):
+        p = flb.make_params(side, side, ux0=ux, kT=1e-4, seed=200 + k, sample_every=1,
+                            block_steps=10)
+        reqs.append((p, n))
+    budget = 64 << 20
+    mix = _serve(flb, reqs, budget, slots=4, chunk=20)
+    for k, (p, n) in enumerate(reqs):
+        alone = _serve(flb, [(p, n)], budget, slots=1, chunk=20)[0]
+        np.testing.assert_array_equal(mix[k]["cov"]["cov_f"], alone["cov"]["cov_f"])
+        L = flb.Lattice(p)
+        L.step(n)
+        np.testing.assert_array_equal(mix[k]["cov"]["cov_f"], L.covariance()["cov_f"])
+
+
+@pytest.mark.parametrize("chunk", [0, 6])
+def test_ensemble_mixed_compute_classes_equal_alone(flb, chunk):
+    """Replicas above |u0| = 0.25 (FP64 collision on FP32 storage) and below
+    it (FP32 collision) in one ensemble: two launches per step, and every
+    replica equals its own single-lattice run."""
+    ps = [flb.make_params(40, 12, ux0=ux, kT=1e-4, seed=300 + k, sample_every=2, block_steps=6)
+          for k, ux in enumerate([0.1, 0.3, 0.0, 0.27, 0.2])]
+    E = flb.Ensemble(ps, graph_chunk=chunk)
+    E.step(25)
+    for i, p in enumerate(ps):
+        L = flb.Lattice(p)
+        L.step(25)
+        np.testing.assert_array_equal(E.populations(i), L.populations())
+        np.testing.assert_array_equal(E.covariance(i)["cov_f"], L.covariance()["cov_f"])
