@@ -278,7 +278,7 @@ def main():
         return
     if args.workload == "serve":
         r = run_serving(F, torch, nreq=args.requests or 400, rate=args.rate)
-        print(json.dumps({"workload": "serving, Poisson 50/s", **r}), flush=True)
+        print(json.dumps({"workload": f"serving, Poisson {args.rate:g}/s", **r}), flush=True)
         return
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     r = run_large(F, torch, args.steps, args.warmup, nx=args.nx, every=args.sk_every,
