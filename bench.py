@@ -243,7 +243,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="large", choices=["large", "ensemble", "serve"])
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "ensemble", "serve", "paper"])
     ap.add_argument("--requests", type=int, default=None,
                     help="serving window (default 40 in the main line, 400 with --workload serve)")
     ap.add_argument("--no-serving", action="store_true")
@@ -275,6 +276,14 @@ def main():
     if args.workload == "ensemble":
         r = run_ensemble(F, torch, args.steps, args.warmup)
         print(json.dumps({"workload": "64 x 128^2 FP32 ensemble, hipGraph", **r}), flush=True)
+        return
+    if args.workload == "paper":
+        from paper_1204_6734_amd import analysis as A
+        t0 = time.perf_counter()
+        r = A.paper_experiments(F)
+        print(json.dumps({"workload": "the paper's 21x21 sweeps (Hermite, f-norm local, f-norm "
+                                      "table), mu/rho0 = 1e-6", "seconds": time.perf_counter() - t0,
+                          **r}), flush=True)
         return
     if args.workload == "serve":
         r = run_serving(F, torch, nreq=args.requests or 400, rate=args.rate)

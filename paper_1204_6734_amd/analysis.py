@@ -46,15 +46,80 @@ def velocity_sweep(F, basis: int, us, nx: int = 21, ny: int = 21, kT: float = 1e
     mu_rho = noise_strength(kT) * rho0
     key, sekey = (("cov_m_hermite", "se_cov_m_hermite") if basis == F.BASIS_HERMITE
                   else ("cov_m_fnorm_u0", "se_cov_m"))
-    dev, se = [], []
+    dev, se, cov_f, se_f = [], [], [], []
     nsamples = 0
     for k in range(len(us)):
         c = E.covariance(k)
         dev.append(c[key] / mu_rho - np.eye(9))
         se.append(c[sekey] / mu_rho)
+        cov_f.append(c["cov_f"] / noise_strength(kT))
+        se_f.append(c["se_cov_f"] / noise_strength(kT))
         nsamples = c["nsamples"]
     E.close()
-    return {"us": us, "dev": np.array(dev), "se": np.array(se), "nsamples": nsamples}
+    return {"us": us, "dev": np.array(dev), "se": np.array(se), "cov_f": np.array(cov_f),
+            "se_f": np.array(se_f), "nsamples": nsamples}
+
+
+def equilibrium(rho: float, ux: float, uy: float) -> np.ndarray:
+    """f_i^0(rho, u) of eq. (A1) on the D2Q9 set (for normalising results)."""
+    vx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)
+    vy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], float)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    cu = vx * ux + vy * uy
+    return w * rho * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (ux * ux + uy * uy))
+
+
+def paper_experiments(F, kT: float = 1e-6 / 3, therm: int = 100_000, steps: int = 1_000_000,
+                      sk_steps: int = 200_000, sk_every: int = 10) -> dict:
+    """The paper's 21 x 21 experiments on the GPU (Secs. III and IV): the
+    noise strength of its rho0 = 1e6 (mu / rho0 = 1e-6), u_x0 = -0.25 ... 0.25,
+    equilibration then sampling every step, for the Hermite norm, the local
+    f-norm and the table f-norm.  Returns per scheme the variances of the
+    populations against f_i^0 (Figs. 2-4, 12-15), the moment variances (Figs.
+    6, 16, 17), the l/q maps and the printed q / l summary (Figs. 7, 18), and
+    S_k / R_k deviations at u_x0 = 0, 0.1, 0.2 (Figs. 8-10, 19-21)."""
+    us = np.round(np.arange(-0.25, 0.2501, 0.05), 10)
+    out = {"kT": kT, "mu_over_rho0": noise_strength(kT), "us": us.tolist(), "steps": steps,
+           "therm": therm}
+    schemes = (("hermite", F.BASIS_HERMITE), ("fnorm_local", F.BASIS_FNORM_LOCAL),
+               ("fnorm_lut", F.BASIS_FNORM_LUT))
+    import sys
+    for name, basis in schemes:
+        print(f"paper experiments: {name} sweep", file=sys.stderr, flush=True)
+        r = velocity_sweep(F, basis, us, kT=kT, therm=therm, steps=steps, block_steps=10_000)
+        l, q, sl, sq = lq_maps(us, r["dev"], r["se"])
+        f0 = np.array([equilibrium(1.0, u, 0.0) for u in us])
+        var_f = np.array([np.diag(c) for c in r["cov_f"]])
+        res = {
+            # <df_i^2> / (mu f_i^0(u0)) - 1 per velocity and direction
+            "var_f_over_f0_minus_1": (var_f / f0 - 1).tolist(),
+            "var_m_minus_1": [np.diag(d).tolist() for d in r["dev"]],
+            "q_diag": np.diag(q).tolist(), "q_diag_se": np.diag(sq).tolist(),
+            "l_max_abs": float(np.abs(l).max()),
+            "q": {"rho": q[0, 0], "Pi_xx-yy": q[3, 3], "j_y": q[2, 2]},
+            "nsamples": int(r["nsamples"]),
+        }
+        sk = {}
+        for u in (0.0, 0.1, 0.2):
+            p = F.make_params(21, 21, ux0=u, kT=kT, basis=basis, seed=99, sk_every=sk_every)
+            L = F.Lattice(p)
+            L.step(therm)
+            L.reset_stats()
+            L.step(sk_steps)
+            m = structure_factor_maps(L, kT)
+            mask = np.ones((21, 21), bool)
+            mask[0, 0] = False
+            sk[f"{u:g}"] = {
+                "S_rho_max_dev_kx_axis": float(np.abs(m["rho"][0, 1:] - 1).max()),
+                "S_jx_max_dev_kx_axis": float(np.abs(m["jx"][0, 1:] - 1).max()),
+                "S_rho_mean_dev": float(np.abs(m["rho"][mask] - 1).mean()),
+                "S_jx_mean_dev": float(np.abs(m["jx"][mask] - 1).mean()),
+                "R_max_abs": float(np.abs(m["R"][mask]).max()),
+            }
+            L.close()
+        res["structure_factors"] = sk
+        out[name] = res
+    return out
 
 
 def lq_maps(us, dev, se=None):
