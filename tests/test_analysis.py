@@ -30,4 +30,4 @@ def test_equilibrium_is_eq_A1():
 
 
 def test_noise_strength():
-    assert A.noise_strength(1e-4) == 3e-4
+    assert abs(A.noise_strength(1e-4) - 3e-4) < 1e-18
