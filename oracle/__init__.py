@@ -29,15 +29,20 @@ INIT_EQUILIBRIUM, INIT_THERMAL, INIT_FIELDS = 0, 1, 2
 AT_LOCAL, AT_U0, AT_HERMITE = 0, 1, 2
 
 
+_SRC3 = os.path.join(_HERE, "flbref3.c")
+
+
 def build(force: bool = False) -> str:
-    """Compile ``libflbref.so`` with gcc (always when ``force``)."""
+    """Compile ``libflbref.so`` (D2Q9 and D3Q19 oracles) with gcc (always when
+    ``force``)."""
+    deps = [_SRC, _SRC3] + [os.path.join(_HERE, h) for h in ("flbref.h", "flbref3.h")]
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(
-        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "flbref.h"))
+        os.path.getmtime(f) for f in deps
     ):
         tmp = _SO + f".tmp{os.getpid()}"
         subprocess.check_call(
             ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-fPIC", "-shared",
-             "-o", tmp, _SRC, "-lm"]
+             "-o", tmp, _SRC, _SRC3, "-lm"]
         )
         os.replace(tmp, _SO)
     return _SO
