@@ -255,6 +255,61 @@ int flb_ensemble_set_launch(flb_ensemble* E, const flb_launch_config* c);
 int flb_lattice_get_launch(flb_lattice* L, flb_launch_config* c);
 int flb_ensemble_get_launch(flb_ensemble* E, flb_launch_config* c);
 
+/* ---------------------------------------------------------- D3Q19 lattices
+ * The same step on the D3Q19 velocity set (the paper's construction carried
+ * over to three dimensions, Sec. V): rest, six face and twelve edge
+ * velocities (opposite pairs adjacent: index 2k-1 <-> 2k), weights 1/3,
+ * 1/18, 1/36, equilibrium of the form of eq. (A1); basis rows = Gram-Schmidt
+ * under the weights of the polynomials 1; v_x, v_y, v_z; v_x v_y, v_x v_z,
+ * v_y v_z, v_x^2 - v_y^2, v_x^2 + v_y^2 - 2 v_z^2, v^2; v_x (v_y^2 + v_z^2),
+ * v_y (v_x^2 + v_z^2), v_z (v_x^2 + v_y^2), v_x (v_y^2 - v_z^2),
+ * v_y (v_z^2 - v_x^2), v_z (v_x^2 - v_y^2); v^4, (2 v_x^2 - v_y^2 - v_z^2) v^2,
+ * (v_y^2 - v_z^2) v^2; f-norm rows = their Gram-Schmidt under f^0(1, u)
+ * (eqs. (27)-(30)); fifteen non-conserved modes a = 4..18 with their own
+ * tau and the amplitude of eq. (20).  Noise: four Philox4x32-10 blocks per
+ * site and step, counter (site, block 0..3, step lo, step hi), key = seed;
+ * the top 24 bits of the sixteen words as uniforms (U + 1/2) 2^-24,
+ * Box-Muller on consecutive pairs, the first fifteen Gaussians.  Sites are
+ * (z ny + y) nx + x; populations cross the boundary unshifted in FP64,
+ * [19][nz][ny][nx].  FP32-shifted lattices compute in FP32 at every u0.
+ * Lattices only (no ensembles, server or structure factors). */
+typedef struct {
+  int32_t nx, ny, nz;      /* periodic, >= 3 each, 19 nx ny nz < 2^32             */
+  int32_t precision;       /* FLB_FP64 or FLB_FP32_SHIFTED                         */
+  int32_t basis;           /* FLB_BASIS_FNORM_LOCAL or FLB_BASIS_HERMITE           */
+  int32_t sample_every;    /* correlator sampling interval (0: none)              */
+  int32_t block_steps;     /* time-block length for standard errors               */
+  int32_t pad_;
+  double rho0, ux0, uy0, uz0;
+  double kT;               /* mu = 3 kT                                            */
+  double tau[15];          /* modes a = 4..18, each > 1/2                          */
+  uint64_t seed;
+} flb3_params;
+
+typedef struct {
+  uint64_t nsamples, nblocks;
+  double mean_df[19];      /* <f_i> - f_i^0(rho0, u0)                              */
+  double cov_f[361];       /* <df_i df_j>, empirical-mean centred                  */
+  double se_cov_f[361];    /* time-block standard errors (NaN below two blocks)    */
+} flb3_cov;
+
+typedef struct flb3_lattice flb3_lattice;
+/* Equilibrium start f = f^0(rho0, u0); FLB_E_ARG / FLB_E_INVALID_VELOCITY /
+ * FLB_E_OOM / FLB_E_HIP as for flb_lattice_create. */
+int flb3_lattice_create(const flb3_params* p, void* hip_stream, flb3_lattice** out);
+int flb3_lattice_set_populations(flb3_lattice* L, const double* f, uint64_t t);
+/* Asynchronous; errors of the kernels surface at the next sync or read. */
+int flb3_lattice_step(flb3_lattice* L, uint64_t nsteps);
+int flb3_lattice_sync(flb3_lattice* L);
+int flb3_lattice_read_populations(flb3_lattice* L, double* f);
+int flb3_lattice_read_covariance(flb3_lattice* L, flb3_cov* out);
+int flb3_lattice_reset_stats(flb3_lattice* L);
+uint64_t flb3_lattice_time(flb3_lattice* L);
+int64_t flb3_lattice_error_step(flb3_lattice* L);
+int flb3_lattice_profile(flb3_lattice* L, int32_t on);
+int flb3_lattice_kernel_time(flb3_lattice* L, double* ms, uint64_t* launches);
+void flb3_lattice_destroy(flb3_lattice* L);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of simulation requests of mixed size, temperature and
  * background velocity.  Requests wait in FIFO order; one is admitted as soon

@@ -74,6 +74,22 @@ class LaunchConfig(C.Structure):
                 ("ms_per_step", C.c_double)]
 
 
+class Params3(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("precision", C.c_int32),
+        ("basis", C.c_int32), ("sample_every", C.c_int32), ("block_steps", C.c_int32),
+        ("pad_", C.c_int32), ("rho0", C.c_double), ("ux0", C.c_double), ("uy0", C.c_double),
+        ("uz0", C.c_double), ("kT", C.c_double), ("tau", C.c_double * 15),
+        ("seed", C.c_uint64),
+    ]
+
+
+class Cov3(C.Structure):
+    _fields_ = [("nsamples", C.c_uint64), ("nblocks", C.c_uint64),
+                ("mean_df", C.c_double * 19), ("cov_f", C.c_double * 361),
+                ("se_cov_f", C.c_double * 361)]
+
+
 class FlbError(RuntimeError):
     def __init__(self, code: int, what: str, msg: str):
         super().__init__(f"{what} failed ({code}): {msg}")
@@ -119,6 +135,15 @@ _SIGS = {
     "flb_ensemble_set_launch": [C.c_void_p, C.POINTER(LaunchConfig)],
     "flb_lattice_get_launch": [C.c_void_p, C.POINTER(LaunchConfig)],
     "flb_ensemble_get_launch": [C.c_void_p, C.POINTER(LaunchConfig)],
+    "flb3_lattice_create": [C.POINTER(Params3), C.c_void_p, C.POINTER(C.c_void_p)],
+    "flb3_lattice_set_populations": [C.c_void_p, C.POINTER(C.c_double), C.c_uint64],
+    "flb3_lattice_step": [C.c_void_p, C.c_uint64],
+    "flb3_lattice_sync": [C.c_void_p],
+    "flb3_lattice_read_populations": [C.c_void_p, C.POINTER(C.c_double)],
+    "flb3_lattice_read_covariance": [C.c_void_p, C.POINTER(Cov3)],
+    "flb3_lattice_reset_stats": [C.c_void_p],
+    "flb3_lattice_profile": [C.c_void_p, C.c_int32],
+    "flb3_lattice_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
     "flb_server_create": [C.POINTER(ServerConfig), C.c_void_p, C.POINTER(C.c_void_p)],
     "flb_server_submit": [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)],
     "flb_server_pump": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
@@ -128,7 +153,7 @@ _SIGS = {
                          C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_double)],
 }
 _VOID = {"flb_lattice_destroy": [C.c_void_p], "flb_ensemble_destroy": [C.c_void_p],
-         "flb_server_destroy": [C.c_void_p]}
+         "flb_server_destroy": [C.c_void_p], "flb3_lattice_destroy": [C.c_void_p]}
 
 
 def load(path: str | None = None):
@@ -162,7 +187,9 @@ def load(path: str | None = None):
     lib.flb_lattice_checkpoint_bytes.restype = C.c_size_t
     lib.flb_server_request_bytes.argtypes = [C.POINTER(Request)]
     lib.flb_server_request_bytes.restype = C.c_size_t
-    for name in ("flb_lattice_time", "flb_ensemble_time"):
+    lib.flb3_lattice_error_step.argtypes = [C.c_void_p]
+    lib.flb3_lattice_error_step.restype = C.c_int64
+    for name in ("flb_lattice_time", "flb_ensemble_time", "flb3_lattice_time"):
         getattr(lib, name).argtypes = [C.c_void_p]
         getattr(lib, name).restype = C.c_uint64
     lib.flb_lattice_error_step.argtypes = [C.c_void_p]
@@ -405,6 +432,83 @@ class Ensemble(_Tunable):
         ms = C.c_double()
         n = C.c_uint64()
         _check(load().flb_ensemble_kernel_time(self.h, C.byref(ms), C.byref(n)), "kernel_time")
+        return ms.value, n.value
+
+
+def make_params3(nx, ny, nz, rho0=1.0, ux0=0.0, uy0=0.0, uz0=0.0, kT=0.0, tau=(1.0,) * 15,
+                 seed=1, precision=FP32_SHIFTED, basis=BASIS_FNORM_LOCAL, sample_every=0,
+                 block_steps=0) -> Params3:
+    """D3Q19 parameters (flb3_params)."""
+    tau = tuple(tau)
+    if len(tau) == 1:
+        tau = tau * 15
+    return Params3(nx, ny, nz, precision, basis, sample_every, block_steps, 0, rho0, ux0, uy0,
+                   uz0, kT, (C.c_double * 15)(*tau), seed)
+
+
+class Lattice3:
+    """One periodic D3Q19 lattice on the GPU (flb3_lattice_*)."""
+
+    def __init__(self, p: Params3, stream=None):
+        lib = load()
+        self.p = p
+        h = C.c_void_p()
+        _check(lib.flb3_lattice_create(C.byref(p), _stream_ptr(stream), C.byref(h)),
+               "lattice3_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().flb3_lattice_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_populations(self, f, t: int = 0):
+        fa = np.ascontiguousarray(f, dtype=np.float64)
+        _check(load().flb3_lattice_set_populations(self.h, _dp(fa), t), "set_populations3")
+
+    def step(self, n: int):
+        _check(load().flb3_lattice_step(self.h, n), "step3")
+
+    def sync(self):
+        _check(load().flb3_lattice_sync(self.h), "sync3")
+
+    @property
+    def t(self) -> int:
+        return int(load().flb3_lattice_time(self.h))
+
+    @property
+    def error_step(self) -> int:
+        return int(load().flb3_lattice_error_step(self.h))
+
+    def populations(self) -> np.ndarray:
+        f = np.empty((19, self.p.nz, self.p.ny, self.p.nx))
+        _check(load().flb3_lattice_read_populations(self.h, _dp(f)), "read3")
+        return f
+
+    def covariance(self) -> dict:
+        c = Cov3()
+        _check(load().flb3_lattice_read_covariance(self.h, C.byref(c)), "cov3")
+        return {"nsamples": int(c.nsamples), "nblocks": int(c.nblocks),
+                "mean_df": np.array(c.mean_df[:]),
+                "cov_f": np.array(c.cov_f[:]).reshape(19, 19),
+                "se_cov_f": np.array(c.se_cov_f[:]).reshape(19, 19)}
+
+    def reset_stats(self):
+        _check(load().flb3_lattice_reset_stats(self.h), "reset3")
+
+    def profile(self, on: bool = True):
+        _check(load().flb3_lattice_profile(self.h, 1 if on else 0), "profile3")
+
+    def kernel_time(self):
+        ms = C.c_double()
+        n = C.c_uint64()
+        _check(load().flb3_lattice_kernel_time(self.h, C.byref(ms), C.byref(n)), "kernel_time3")
         return ms.value, n.value
 
 

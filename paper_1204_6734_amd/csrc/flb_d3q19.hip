@@ -1,0 +1,502 @@
+// flb_d3q19.hip — the fluctuating f-norm step on a D3Q19 lattice (gfx950).
+//
+// The paper builds its method on D2Q9 and notes that it carries over to
+// other velocity sets (Sec. V).  This is that generalisation: the same
+// collision in moment space (Sec. II, eq. (6)) with the FDT amplitude of
+// eq. (20), in the basis obtained by Gram-Schmidt of 19 polynomial rows
+// under g = f^0(1, u) (Sec. IV, eqs. (27)-(32)); the tables are in
+// d3q19_tables.hpp.  As in D2Q9 the conserved rows are 1 and sqrt3 (v - u)
+// in closed form and the fifteen others follow from the Cholesky factor of
+// the 15x15 Schur complement of the Gram matrix, whose entries are
+// quadratic polynomials in u (table kG3); populations are stored shifted by
+// f^0(rho0, u0), SoA [19][nz][ny][nx], updated in place with the two-phase
+// (AA) pattern, one 64 x 4 tile of one z plane per 256-thread workgroup.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "d3q19_tables.hpp"
+#include "flb_d3q19.hpp"
+#include "flb_device.hpp"
+
+namespace flb {
+namespace d3q19 {
+
+constexpr double kS3 = 1.7320508075688772935;
+
+template <typename R>
+struct Const3 {
+  R rho0, u0[3];
+  R rt[15], xc[15];
+};
+
+template <typename R>
+__device__ __forceinline__ Const3<R> const3(const Desc3& d);
+template <>
+__device__ __forceinline__ Const3<float> const3<float>(const Desc3& d) {
+  Const3<float> c;
+  c.rho0 = (float)d.rho0;
+  for (int a = 0; a < 3; ++a) c.u0[a] = (float)d.u0[a];
+  for (int a = 0; a < 15; ++a) {
+    c.rt[a] = (float)d.rt[a];
+    c.xc[a] = (float)d.xc[a];
+  }
+  return c;
+}
+template <>
+__device__ __forceinline__ Const3<double> const3<double>(const Desc3& d) {
+  Const3<double> c;
+  c.rho0 = d.rho0;
+  for (int a = 0; a < 3; ++a) c.u0[a] = d.u0[a];
+  for (int a = 0; a < 15; ++a) {
+    c.rt[a] = d.rt[a];
+    c.xc[a] = d.xc[a];
+  }
+  return c;
+}
+
+// Fifteen Gaussians of variance v (the local density) for one site and
+// step: four Philox4x32-10 blocks with counter (site, block, step lo, step
+// hi), key = seed; the top 24 bits of the sixteen words give uniforms
+// (U + 1/2) 2^-24, and Box-Muller on consecutive pairs.
+template <typename R>
+__device__ __forceinline__ void gaussians15(uint32_t k0, uint32_t k1, uint32_t site, uint64_t t,
+                                            R v, R N[15]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint4 w = philox4x32_10_site(site, (uint32_t)c, (uint32_t)t, (uint32_t)(t >> 32), k0, k1);
+    const uint32_t U[4] = {w.x >> 8, w.y >> 8, w.z >> 8, w.w >> 8};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int k = 4 * c + 2 * p;
+      R n0, n1;
+      box_muller<R, 24>(U[2 * p], U[2 * p + 1], v, n0, n1);
+      if (k < 15) N[k] = n0;
+      if (k + 1 < 15) N[k + 1] = n1;
+    }
+  }
+}
+
+// One collision on shifted populations h (in place); returns error bits.
+template <typename R, int BASIS>
+__device__ __forceinline__ int collide3(R h[19], const Const3<R>& C, uint32_t k0, uint32_t k1,
+                                        int noise, uint32_t site, uint64_t t) {
+  // moments of h in the basis rows (h = f - f^0(rho0, u0))
+  R M[19];
+#pragma unroll
+  for (int b = 0; b < 19; ++b) {
+    R s = R(0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+      if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * h[i];
+    M[b] = s;
+  }
+  const R drho = M[0];
+  const R rho = C.rho0 + drho;
+  const R rs3 = R(1.0 / kS3);
+  R du[3], u[3], su[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // rho (u - u0) = (j - rho0 u0) - (rho - rho0) u0, with j - rho0 u0 = M^a / sqrt3
+    du[a] = (M[1 + a] * rs3 - drho * C.u0[a]) * rcp_t(rho);
+    u[a] = C.u0[a] + du[a];
+    su[a] = u[a] + C.u0[a];
+  }
+  if (!(rho > R(0)) || !(du[0] == du[0]) || !(du[1] == du[1]) || !(du[2] == du[2]))
+    return kErrNonFinite;
+  // monomials of u (and their changes from u0, from small quantities)
+  const R mono[9] = {u[0], u[1], u[2], u[0] * u[0], u[1] * u[1], u[2] * u[2],
+                     u[0] * u[1], u[0] * u[2], u[1] * u[2]};
+  const R dmono[9] = {du[0], du[1], du[2], du[0] * su[0], du[1] * su[1], du[2] * su[2],
+                      du[0] * u[1] + C.u0[0] * du[1], du[0] * u[2] + C.u0[0] * du[2],
+                      du[1] * u[2] + C.u0[1] * du[2]};
+  // non-equilibrium moments d_b = M_b(f) - M_b(f^0(rho, u)), b = 4..18:
+  // M_b(f^0(rho,u)) - M_b(f^0(rho0,u0)) = drho pi_b(u) + rho0 (pi_b(u) - pi_b(u0))
+  R d[15];
+#pragma unroll
+  for (int b = 4; b < 19; ++b) {
+    R pi = R(0), dpi = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      if (kPi3[b][k] != 0.0) {
+        pi += R(kPi3[b][k]) * mono[k];
+        dpi += R(kPi3[b][k]) * dmono[k];
+      }
+    d[b - 4] = M[b] - (drho * pi + C.rho0 * dpi);
+  }
+  R N[15];
+#pragma unroll
+  for (int a = 0; a < 15; ++a) N[a] = R(0);
+  if (noise) gaussians15<R>(k0, k1, site, t, rho, N);
+
+  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  if (BASIS == 1) {
+    // Hermite-type rows with n = w m: relax d directly
+    R Y[15];
+#pragma unroll
+    for (int a = 0; a < 15; ++a) Y[a] = C.xc[a] * N[a] - C.rt[a] * d[a];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      R s = R(0);
+#pragma unroll
+      for (int b = 4; b < 19; ++b)
+        if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * Y[b - 4];
+      h[i] += R(kW3[i]) * s;
+    }
+    return 0;
+  }
+
+  // g_i = f_i^0(1, u) and the validity of the f-norm
+  R g[19];
+  R gmin = R(1);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const R cu = R(kC3[i][0]) * u[0] + R(kC3[i][1]) * u[1] + R(kC3[i][2]) * u[2];
+    g[i] = R(kW3[i]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+    gmin = fmin(gmin, g[i]);
+  }
+  if (!(gmin > R(0))) return kErrInvalidVelocity;
+
+  // projections of rows 4..18 on the conserved f-norm rows 1, sqrt3 (v_a - u_a)
+  R P0[15], P[3][15];
+#pragma unroll
+  for (int b = 4; b < 19; ++b) {
+    R g0 = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      if (kPi3[b][k] != 0.0) g0 += R(kPi3[b][k]) * mono[k];
+    P0[b - 4] = g0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      R ga = R(0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if (kG3[1 + a][b][k] != 0.0) ga += R(kG3[1 + a][b][k]) * mono[k];
+      P[a][b - 4] = ga - R(kS3) * u[a] * g0;
+    }
+  }
+  // Schur complement of the Gram matrix (lower part, row-major packed),
+  // factorised in place: L[i][j] (j < i) and inverse pivots r[i]
+  R L[120];
+#pragma unroll
+  for (int a = 0; a < 15; ++a)
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      R G = a == b ? R(1) - R(1.5) * uu : R(0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if (kG3[4 + a][4 + b][k] != 0.0) G += R(kG3[4 + a][4 + b][k]) * mono[k];
+      G -= P0[a] * P0[b] + P[0][a] * P[0][b] + P[1][a] * P[1][b] + P[2][a] * P[2][b];
+      L[a * (a + 1) / 2 + b] = G;
+    }
+  R r[15];
+#pragma unroll
+  for (int j = 0; j < 15; ++j) {
+    R dj = L[j * (j + 1) / 2 + j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+    r[j] = rsqrt_t(dj);
+#pragma unroll
+    for (int i = j + 1; i < 15; ++i) {
+      R s = L[i * (i + 1) / 2 + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+      L[i * (i + 1) / 2 + j] = s * r[j];
+    }
+  }
+  // M~ = L^-1 d, relaxation and noise, y = L^-T dM~
+  R x[15];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) {
+    R s = d[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= L[i * (i + 1) / 2 + k] * x[k];
+    x[i] = s * r[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 15; ++i) x[i] = C.xc[i] * N[i] - C.rt[i] * x[i];
+  R y[15];
+#pragma unroll
+  for (int i = 14; i >= 0; --i) {
+    R s = x[i];
+#pragma unroll
+    for (int k = i + 1; k < 15; ++k) s -= L[k * (k + 1) / 2 + i] * y[k];
+    y[i] = s * r[i];
+  }
+  // df_i = g_i [ sum_b m_i^b y_b - A0 - sum_a m~^a_i A_a ],
+  // m~^a_i = sqrt3 (c_ia - u_a): = g_i [ sigma_i + K - sum_a c_ia B_a ]
+  R A0 = R(0), A[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int b = 0; b < 15; ++b) {
+    A0 += P0[b] * y[b];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) A[a] += P[a][b] * y[b];
+  }
+  const R K = R(kS3) * (u[0] * A[0] + u[1] * A[1] + u[2] * A[2]) - A0;
+  const R B[3] = {R(kS3) * A[0], R(kS3) * A[1], R(kS3) * A[2]};
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    R s = K;
+#pragma unroll
+    for (int b = 4; b < 19; ++b)
+      if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * y[b - 4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC3[i][a] != 0) s -= R(kC3[i][a]) * B[a];
+    h[i] += g[i] * s;
+  }
+  return 0;
+}
+
+// --------------------------------------------------------------- kernels
+__device__ __forceinline__ double select_bits(uint64_t mask, double a, double b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  return __builtin_bit_cast(double, (ua & mask) | (ub & ~mask));
+}
+
+// Sum over the wavefront of 32 per-lane values; lanes 2v and 2v+1 end with
+// the total of value v (five butterfly passes halve the values per lane).
+__device__ __forceinline__ double wave_sum32(double (&v)[32], int lane) {
+#pragma unroll
+  for (int off = 32, n = 16; off >= 2; off >>= 1, n >>= 1) {
+    const uint64_t up = (lane & off) ? ~0ull : 0ull;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const double send = select_bits(up, v[k], v[k + n]);
+      const double keep = select_bits(up, v[k + n], v[k]);
+      v[k] = keep + __shfl_xor(send, off, 64);
+    }
+  }
+  return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
+// Statistic q of the correlator sums: df_i (q < 19) or df_i df_j (i <= j,
+// row-major) as index pairs, j = -1 for the first moments.
+struct StatIndex {
+  int i[kNStat3], j[kNStat3];
+};
+constexpr StatIndex stat_index() {
+  StatIndex s{};
+  int q = 0;
+  for (int i = 0; i < 19; ++i, ++q) {
+    s.i[q] = i;
+    s.j[q] = -1;
+  }
+  for (int i = 0; i < 19; ++i)
+    for (int j = i; j < 19; ++j, ++q) {
+      s.i[q] = i;
+      s.j[q] = j;
+    }
+  return s;
+}
+constexpr StatIndex kStat = stat_index();
+
+// Correlator sums of df = h (the 209 statistics above), added to this
+// tile's partials; the whole workgroup calls this.  Seven groups of 32
+// values are reduced over the wavefront by transposing butterflies.
+template <typename R>
+__device__ __forceinline__ void sample3(const R h[19], bool active, double* partials) {
+  __shared__ double red[4][224];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double df[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) df[i] = active ? (double)h[i] : 0.0;
+#pragma unroll
+  for (int group = 0; group < 7; ++group) {
+    double v[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int q = group * 32 + k;
+      if (q >= kNStat3)
+        v[k] = 0.0;
+      else if (kStat.j[q] < 0)
+        v[k] = df[kStat.i[q]];
+      else
+        v[k] = df[kStat.i[q]] * df[kStat.j[q]];
+    }
+    const double tot = wave_sum32(v, lane);
+    if ((lane & 1) == 0) red[wave][group * 32 + (lane >> 1)] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNStat3)
+    partials[threadIdx.x] += (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                             (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__device__ __forceinline__ uint32_t cell(int x, int y, int z, const Desc3& d) {
+  return ((uint32_t)z * d.ny + y) * d.nx + x;
+}
+
+// Element of the population array a site reads in phase ODD for direction
+// i: even phase plane i at the site; odd phase plane opp(i) at x - c_i.
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+template <typename S, typename R, int BASIS, bool SAMPLE, int ODD>
+__global__ __launch_bounds__(256) void step3_kernel(const Desc3* __restrict__ desc,
+                                                    const uint64_t* __restrict__ clock,
+                                                    uint32_t step_idx) {
+  const Desc3& d = *desc;
+  const uint64_t t = *clock + step_idx;
+  const int tile = blockIdx.x;
+  const int z = tile / d.tiles_xy;
+  const int r = tile - z * d.tiles_xy;
+  const int ty = r / d.tiles_x, tx = r - ty * d.tiles_x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x = tx * 64 + (threadIdx.x & 63), y = ty * 4 + wave;
+  const bool active = x < d.nx && y < d.ny;
+  const uint32_t N = (uint32_t)d.nx * d.ny * d.nz;
+  S* pop = reinterpret_cast<S*>(d.pop);
+  uint32_t idx[19];
+  R h[19];
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      if (!ODD) {
+        idx[i] = (uint32_t)i * N + cell(x, y, z, d);
+      } else {
+        const int xs = wrap(x - kC3[i][0], d.nx), ys = wrap(y - kC3[i][1], d.ny);
+        const int zs = wrap(z - kC3[i][2], d.nz);
+        idx[i] = (uint32_t)kOpp3[i] * N + cell(xs, ys, zs, d);
+      }
+      h[i] = (R)pop[idx[i]];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) h[i] = R(0);
+  }
+  if (SAMPLE) {
+    if (d.sample_every > 0 && t % (uint64_t)d.sample_every == 0)
+      sample3<R>(h, active, d.partials + (size_t)tile * kNStat3);
+  }
+  if (!active) return;
+  const Const3<R> C = const3<R>(d);
+  const int e = collide3<R, BASIS>(h, C, d.k0, d.k1, d.noise, cell(x, y, z, d), t);
+  if (e) {
+    atomicOr(d.err, e);
+    atomicMin(d.err_step, (unsigned long long)t);
+    return;
+  }
+  // the post-collision value of direction opp(i) goes back to idx[i]
+#pragma unroll
+  for (int i = 0; i < 19; ++i) pop[idx[i]] = (S)h[kOpp3[i]];
+}
+
+// State I/O: f (unshifted FP64, [19][nz][ny][nx]) <-> storage at phase odd
+// (odd: the reversed, un-streamed layout the next odd step reads).
+template <typename S>
+__global__ void io3_kernel(S* pop, double* f, Desc3 d, int odd, int to_storage) {
+  const uint32_t N = (uint32_t)d.nx * d.ny * d.nz;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const int x = (int)(s % (uint32_t)d.nx);
+  const int y = (int)((s / (uint32_t)d.nx) % (uint32_t)d.ny);
+  const int z = (int)(s / ((uint32_t)d.nx * d.ny));
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    uint32_t e;
+    if (!odd) {
+      e = (uint32_t)i * N + s;
+    } else {
+      // f_i(x) is held in plane opp(i) at x - c_i
+      const int xs = wrap(x - kC3[i][0], d.nx), ys = wrap(y - kC3[i][1], d.ny);
+      const int zs = wrap(z - kC3[i][2], d.nz);
+      e = (uint32_t)kOpp3[i] * N + ((uint32_t)zs * d.ny + ys) * d.nx + xs;
+    }
+    if (to_storage)
+      pop[e] = (S)(f[(size_t)i * N + s] - d.shift[i]);
+    else
+      f[(size_t)i * N + s] = (double)pop[e] + d.shift[i];
+  }
+}
+
+// Time blocks of the correlator sums (nstat values per record).
+__global__ void close_block3_kernel(double* partials, int ntiles, double* record) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= kNStat3) return;
+  double s = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    s += partials[(size_t)t * kNStat3 + v];
+    partials[(size_t)t * kNStat3 + v] = 0.0;
+  }
+  record[v] = s;
+}
+
+__global__ void merge_blocks3_kernel(double* rec, int nhalf) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= kNStat3) return;
+  for (int b = 0; b < nhalf; ++b)
+    rec[(size_t)b * kNStat3 + v] =
+        rec[(size_t)(2 * b) * kNStat3 + v] + rec[(size_t)(2 * b + 1) * kNStat3 + v];
+}
+
+__global__ void open_sum3_kernel(const double* partials, int ntiles, double* out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= kNStat3) return;
+  double s = 0.0;
+  for (int t = 0; t < ntiles; ++t) s += partials[(size_t)t * kNStat3 + v];
+  out[v] = s;
+}
+
+__global__ void fill3_kernel(double* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// ------------------------------------------------------------- launchers
+template <typename S, typename R, int BASIS>
+static hipError_t step3_t(bool sample, int odd, int ntiles, const Desc3* d,
+                          const uint64_t* clock, uint32_t k, hipStream_t st) {
+  const dim3 g(ntiles), b(256);
+  if (sample) {
+    if (odd)
+      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, true, 1>), g, b, 0, st, d, clock, k);
+    else
+      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, true, 0>), g, b, 0, st, d, clock, k);
+  } else {
+    if (odd)
+      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, false, 1>), g, b, 0, st, d, clock, k);
+    else
+      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, false, 0>), g, b, 0, st, d, clock, k);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step3(int storage, int basis, bool sample, int odd, int ntiles, const Desc3* d,
+                        const uint64_t* clock, uint32_t k, hipStream_t st) {
+  if (storage == 0)
+    return basis == 1 ? step3_t<double, double, 1>(sample, odd, ntiles, d, clock, k, st)
+                      : step3_t<double, double, 0>(sample, odd, ntiles, d, clock, k, st);
+  return basis == 1 ? step3_t<float, float, 1>(sample, odd, ntiles, d, clock, k, st)
+                    : step3_t<float, float, 0>(sample, odd, ntiles, d, clock, k, st);
+}
+
+hipError_t launch_io3(int storage, void* pop, double* f, const Desc3& d, int odd, int to_storage,
+                      hipStream_t st) {
+  const uint32_t N = (uint32_t)d.nx * d.ny * d.nz;
+  const dim3 g((N + 255) / 256), b(256);
+  if (storage == 0)
+    hipLaunchKernelGGL(io3_kernel<double>, g, b, 0, st, (double*)pop, f, d, odd, to_storage);
+  else
+    hipLaunchKernelGGL(io3_kernel<float>, g, b, 0, st, (float*)pop, f, d, odd, to_storage);
+  return hipGetLastError();
+}
+
+hipError_t launch_close_block3(double* partials, int ntiles, double* record, hipStream_t st) {
+  hipLaunchKernelGGL(close_block3_kernel, dim3(1), dim3(256), 0, st, partials, ntiles, record);
+  return hipGetLastError();
+}
+hipError_t launch_merge_blocks3(double* rec, int nhalf, hipStream_t st) {
+  hipLaunchKernelGGL(merge_blocks3_kernel, dim3(1), dim3(256), 0, st, rec, nhalf);
+  return hipGetLastError();
+}
+hipError_t launch_open_sum3(const double* partials, int ntiles, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(open_sum3_kernel, dim3(1), dim3(256), 0, st, partials, ntiles, out);
+  return hipGetLastError();
+}
+hipError_t launch_fill3(double* p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill3_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace d3q19
+}  // namespace flb

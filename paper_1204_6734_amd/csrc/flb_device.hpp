@@ -44,19 +44,19 @@ __device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t k)
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 products, word shuffle, key xor; key bumped by the Weyl
-// increments between rounds.  Here the counter is (site, 0, c2, c3) with
-// c2, c3 and the key wave-uniform: the first round's product of word 2 and
-// the second round's product of word 0 are then wave-uniform too, and are
-// written out so that they run on the scalar unit (18 per-lane products
+// increments between rounds.  Here the counter is (site, c1, c2, c3) with
+// c1, c2, c3 and the key wave-uniform: the first round's product of word 2
+// and the second round's product of word 0 are then wave-uniform too, and
+// are written out so that they run on the scalar unit (18 per-lane products
 // instead of 20).
-__device__ __forceinline__ uint4 philox4x32_10_site(uint32_t site, uint32_t c2, uint32_t c3,
-                                                   uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ uint4 philox4x32_10_site(uint32_t site, uint32_t c1, uint32_t c2,
+                                                   uint32_t c3, uint32_t k0, uint32_t k1) {
   constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
   constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-  // round 1 on (site, 0, c2, c3)
+  // round 1 on (site, c1, c2, c3)
   uint64_t p0 = (uint64_t)M0 * (uint64_t)site;
   uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
-  const uint32_t x1 = (uint32_t)(p1 >> 32) ^ k0;             // uniform
+  const uint32_t x1 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;        // uniform
   const uint32_t y1 = (uint32_t)p1;                          // uniform
   const uint32_t z1 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);      // per lane
   const uint32_t w1 = (uint32_t)p0;                          // per lane
@@ -82,57 +82,78 @@ __device__ __forceinline__ uint4 philox4x32_10_site(uint32_t site, uint32_t c2, 
   return c;
 }
 
-// Six Gaussians of variance v for one (site, step, tag): the 128 Philox bits
-// give six 21-bit integers (top 21 bits of each word, then the low 11 bits
-// of words 0/2 joined with the low 10 bits of words 1/3); u = (U + 1/2)
-// 2^-21 and Box-Muller on the pairs (u0,u1), (u2,u3), (u4,u5), with the
-// variance folded into the radius: r = sqrt(-2 v ln ua).  v = 1 gives unit
-// Gaussians; the collision passes v = rho, the local-density factor of the
-// noise amplitude of eq. (20).
-template <typename R>
-__device__ __forceinline__ void box_muller(uint32_t ua, uint32_t ub, R m2v, R& n0, R& n1);
+// Two Gaussians of variance v from two BITS-bit integers ua, ub (Box-Muller
+// on the uniforms (U + 1/2) 2^-BITS): r = sqrt(-2 v ln ua), angle 2 pi ub.
+template <typename R, int BITS>
+__device__ __forceinline__ void box_muller(uint32_t ua, uint32_t ub, R v, R& n0, R& n1);
 
-template <>
-__device__ __forceinline__ void box_muller<float>(uint32_t ua, uint32_t ub, float m2v, float& n0,
-                                                  float& n1) {
-  // Hardware transcendentals: v_log_f32 is log2, v_sin/v_cos take the angle
-  // in revolutions, so r = sqrt(-2 v ln2 log2 ua) and the angle 2 pi ub needs
-  // no range reduction (ub in (0, 1)).  On these 2^21 inputs they agree
-  // with the correctly rounded values to ~1.3e-7 (absolute, sin/cos) and
-  // ~1.2e-7 (relative, log), the same level as the library routines.
-  // m2v = -2 v ln2.
-  const float fa = __fmaf_rn((float)ua, 4.76837158203125e-07f, 2.384185791015625e-07f);
-  const float fb = __fmaf_rn((float)ub, 4.76837158203125e-07f, 2.384185791015625e-07f);
-  const float r = __builtin_amdgcn_sqrtf(m2v * __builtin_amdgcn_logf(fa));
+// Hardware transcendentals: v_log_f32 is log2, v_sin/v_cos take the angle
+// in revolutions, so r = sqrt(-2 v ln2 log2 ua) and the angle 2 pi ub needs
+// no range reduction (ub in (0, 1)).  On the 2^21 inputs of the D2Q9 draw
+// they agree with the correctly rounded values to ~1.3e-7 (absolute,
+// sin/cos) and ~1.2e-7 (relative, log), the same level as the library
+// routines.
+template <int BITS>
+__device__ __forceinline__ void box_muller_f32(uint32_t ua, uint32_t ub, float v, float& n0,
+                                               float& n1) {
+  constexpr float scale = 1.0f / (float)(1u << BITS), half = 0.5f / (float)(1u << BITS);
+  const float fa = __fmaf_rn((float)ua, scale, half);
+  const float fb = __fmaf_rn((float)ub, scale, half);
+  const float r = __builtin_amdgcn_sqrtf((-1.3862943611198906f * v) * __builtin_amdgcn_logf(fa));
   n0 = r * __builtin_amdgcn_cosf(fb);
   n1 = r * __builtin_amdgcn_sinf(fb);
 }
-
 template <>
-__device__ __forceinline__ void box_muller<double>(uint32_t ua, uint32_t ub, double m2v,
-                                                   double& n0, double& n1) {
-  // m2v = -2 v
-  const double fa = ((double)ua + 0.5) * 4.76837158203125e-07;
-  const double fb = ((double)ub + 0.5) * 9.5367431640625e-07;  // 2u
-  const double r = sqrt(m2v * log(fa));
+__device__ __forceinline__ void box_muller<float, 21>(uint32_t ua, uint32_t ub, float v, float& n0,
+                                                      float& n1) {
+  box_muller_f32<21>(ua, ub, v, n0, n1);
+}
+template <>
+__device__ __forceinline__ void box_muller<float, 24>(uint32_t ua, uint32_t ub, float v, float& n0,
+                                                      float& n1) {
+  box_muller_f32<24>(ua, ub, v, n0, n1);
+}
+
+template <int BITS>
+__device__ __forceinline__ void box_muller_f64(uint32_t ua, uint32_t ub, double v, double& n0,
+                                               double& n1) {
+  constexpr double scale = 1.0 / (double)(1u << BITS);
+  const double fa = ((double)ua + 0.5) * scale;
+  const double fb = ((double)ub + 0.5) * (2.0 * scale);  // 2u
+  const double r = sqrt((-2.0 * v) * log(fa));
   double s, c;
   sincospi(fb, &s, &c);
   n0 = r * c;
   n1 = r * s;
 }
+template <>
+__device__ __forceinline__ void box_muller<double, 21>(uint32_t ua, uint32_t ub, double v,
+                                                       double& n0, double& n1) {
+  box_muller_f64<21>(ua, ub, v, n0, n1);
+}
+template <>
+__device__ __forceinline__ void box_muller<double, 24>(uint32_t ua, uint32_t ub, double v,
+                                                       double& n0, double& n1) {
+  box_muller_f64<24>(ua, ub, v, n0, n1);
+}
 
+// Six Gaussians of variance v for one (site, step, tag): the 128 Philox
+// bits give six 21-bit integers (top 21 bits of each word, then the low 11
+// bits of words 0/2 joined with the low 10 bits of words 1/3) for
+// Box-Muller on the pairs (u0,u1), (u2,u3), (u4,u5).  v = 1 gives unit
+// Gaussians; the collision passes v = rho, the local-density factor of the
+// noise amplitude of eq. (20).
 template <typename R>
 __device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint32_t site,
                                                uint64_t step, uint32_t tag, R v, R N[6]) {
   // counter (site, 0, step lo, step hi ^ tag): a lattice has < 2^32 sites
-  const uint4 w = philox4x32_10_site(site, (uint32_t)step, (uint32_t)(step >> 32) ^ tag, k0, k1);
+  const uint4 w =
+      philox4x32_10_site(site, 0u, (uint32_t)step, (uint32_t)(step >> 32) ^ tag, k0, k1);
   const uint32_t u4 = (w.x & 0x7FFu) | ((w.y & 0x3FFu) << 11);
   const uint32_t u5 = (w.z & 0x7FFu) | ((w.w & 0x3FFu) << 11);
-  // -2 v, times ln 2 where the logarithm is base 2
-  const R m2v = sizeof(R) == 4 ? R(-1.3862943611198906) * v : R(-2) * v;
-  box_muller<R>(w.x >> 11, w.y >> 11, m2v, N[0], N[1]);
-  box_muller<R>(w.z >> 11, w.w >> 11, m2v, N[2], N[3]);
-  box_muller<R>(u4, u5, m2v, N[4], N[5]);
+  box_muller<R, 21>(w.x >> 11, w.y >> 11, v, N[0], N[1]);
+  box_muller<R, 21>(w.z >> 11, w.w >> 11, v, N[2], N[3]);
+  box_muller<R, 21>(u4, u5, v, N[4], N[5]);
 }
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }

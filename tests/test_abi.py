@@ -15,7 +15,7 @@ def declared_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?(?:int|size_t|uint64_t|int64_t|void|char)\s*\**\s*"
-                       r"(flb_\w+)\s*\(", txt, flags=re.M)
+                       r"(flb3?_\w+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
@@ -81,3 +81,18 @@ def test_launch_config_layout_and_null_handles():
     assert lib.flb_ensemble_autotune(None, 3, None, 0, C.byref(n)) == F.E_ARG
     assert lib.flb_lattice_set_launch(None, C.byref(c)) == F.E_ARG
     assert lib.flb_ensemble_get_launch(None, C.byref(c)) == F.E_ARG
+
+
+def test_d3q19_struct_layouts_and_argument_errors():
+    import paper_1204_6734_amd as F
+    lib = F.load()
+    assert C.sizeof(F.Params3) == 8 * 4 + 8 * 5 + 8 * 15 + 8
+    assert F.Params3.rho0.offset == 32 and F.Params3.seed.offset == 192
+    assert C.sizeof(F.Cov3) == 16 + 8 * (19 + 361 * 2)
+    h = C.c_void_p()
+    bad = [F.make_params3(2, 4, 4), F.make_params3(4, 4, 4, tau=(0.5,)),
+           F.make_params3(4, 4, 4, basis=F.BASIS_FNORM_LUT), F.make_params3(4, 4, 4, kT=-1.0),
+           F.make_params3(4, 4, 4, ux0=0.6, uy0=0.6)]
+    codes = [lib.flb3_lattice_create(C.byref(p), None, C.byref(h)) for p in bad]
+    assert codes[:4] == [F.E_ARG] * 4 and codes[4] == F.E_INVALID_VELOCITY
+    assert lib.flb3_lattice_step(None, 1) == F.E_ARG

@@ -1,0 +1,115 @@
+"""D3Q19 lattices on the GPU against the D3Q19 oracle (the generalisation
+of Sec. V; model in include/flb.h): FP64 trajectories to 1e-12 at both
+streaming phases for the local f-norm and the Hermite rows, FP32-shifted
+storage to 1e-5 on the fluctuations, correlator sums, conservation, and the
+ideal-gas covariance at rest within standard errors."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import d3q19 as D
+
+pytestmark = pytest.mark.gpu
+
+TAUS = tuple(np.round(np.random.default_rng(2).uniform(0.6, 1.5, 15), 6))
+
+
+def both(F, nx, ny, nz, precision, basis, **kw):
+    g = F.Lattice3(F.make_params3(nx, ny, nz, precision=precision, basis=basis, **kw))
+    o = D.Lattice(D.make_params(nx, ny, nz, basis=basis, **kw))
+    return g, o
+
+
+def perturbed(nx, ny, nz, u0, seed=1):
+    """Local equilibria with 1 % density and velocity perturbations."""
+    rng = np.random.default_rng(seed)
+    rho = 1 + 0.01 * rng.standard_normal((nz, ny, nx))
+    u = [u0[a] + 0.01 * rng.standard_normal((nz, ny, nx)) for a in range(3)]
+    vx, vy, vz, w = D.velocities()
+    f = np.empty((19, nz, ny, nx))
+    uu = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    for i in range(19):
+        cu = vx[i] * u[0] + vy[i] * u[1] + vz[i] * u[2]
+        f[i] = w[i] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * uu)
+    return f
+
+
+@pytest.mark.parametrize("basis", ["fnorm", "hermite"])
+def test_fp64_trajectory_matches_oracle(flb, basis):
+    b = flb.BASIS_FNORM_LOCAL if basis == "fnorm" else flb.BASIS_HERMITE
+    nx, ny, nz = 70, 6, 5  # two tiles along x, the second ragged
+    kw = dict(ux0=0.1, uy0=-0.05, uz0=0.03, kT=1e-4, tau=TAUS, seed=9)
+    g, o = both(flb, nx, ny, nz, flb.FP64, b, **kw)
+    f = perturbed(nx, ny, nz, (0.1, -0.05, 0.03))
+    g.set_populations(f)
+    o.set_populations(f)
+    for n in (1, 1, 23):
+        g.step(n)
+        o.step(n)
+        fg, fo = g.populations(), o.populations()
+        err = np.abs(fg - fo).max() / np.abs(fo).max()
+        assert err <= 1e-12, (basis, o.t, err)
+
+
+def test_fp32_shifted_matches_fp64_oracle(flb):
+    nx, ny, nz = 40, 8, 6
+    kw = dict(ux0=0.1, uy0=0.05, uz0=0.0, kT=1e-4, tau=TAUS, seed=3)
+    g, o = both(flb, nx, ny, nz, flb.FP32_SHIFTED, flb.BASIS_FNORM_LOCAL, **kw)
+    g.step(200)
+    o.step(200)
+    f0 = D.equilibrium(1.0, 0.1, 0.05, 0.0)[:, None, None, None]
+    dg, do = g.populations() - f0, o.populations() - f0
+    err = np.abs(dg - do).max() / np.abs(do).max()
+    assert err <= 1e-5, err
+
+
+def test_correlator_sums_match_oracle(flb):
+    nx, ny, nz = 20, 5, 4
+    kw = dict(ux0=0.08, kT=1e-4, tau=TAUS, seed=21, sample_every=1, block_steps=5)
+    g, o = both(flb, nx, ny, nz, flb.FP64, flb.BASIS_FNORM_LOCAL, **kw)
+    g.step(30)
+    o.step(30)
+    cg, co = g.covariance(), o.covariance()
+    assert cg["nsamples"] == co["nsamples"] == 30 * nx * ny * nz
+    assert cg["nblocks"] == co["nblocks"] == 6
+    for k in ("mean_df", "cov_f", "se_cov_f"):
+        assert np.abs(cg[k] - co[k]).max() <= 1e-10 * np.abs(co[k]).max(), k
+
+
+def test_conservation_fp64(flb):
+    nx, ny, nz = 33, 7, 5
+    L = flb.Lattice3(flb.make_params3(nx, ny, nz, precision=flb.FP64, ux0=0.12, uz0=-0.04,
+                                      kT=1e-3, tau=TAUS, seed=4))
+    vx, vy, vz, _ = D.velocities()
+    f = L.populations()
+    m0 = f.sum()
+    j0 = [np.tensordot(v, f, axes=(0, 0)).sum() for v in (vx, vy, vz)]
+    L.step(100)
+    f = L.populations()
+    assert abs(f.sum() - m0) < 1e-11 * m0
+    for v, j in zip((vx, vy, vz), j0):
+        assert abs(np.tensordot(v, f, axes=(0, 0)).sum() - j) < 1e-11 * m0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_statistics_at_rest_match_closed_form(flb, prec):
+    """5^3 lattice (odd sides: only the k = 0 mass and momentum are
+    invariant), u0 = 0: <df_i df_j> = mu rho0 [w_i delta_ij - w_i w_j
+    (1 + 3 v_i.v_j) / N] within standard errors."""
+    precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+    n, kT = 5, 1e-4
+    L = flb.Lattice3(flb.make_params3(n, n, n, precision=precision, kT=kT, seed=8,
+                                      sample_every=1, block_steps=500))
+    L.step(500)
+    L.reset_stats()
+    L.step(20000)
+    c = L.covariance()
+    vx, vy, vz, w = D.velocities()
+    C = np.stack([vx, vy, vz], axis=1).astype(float)
+    want = 3 * kT * (np.diag(w) - np.outer(w, w) * (1 + 3 * C @ C.T) / n ** 3)
+    iu = np.triu_indices(19)
+    z = ((c["cov_f"] - want) / c["se_cov_f"])[iu]
+    zmax, zrms = np.abs(z).max(), math.sqrt((z ** 2).mean())
+    print(f"D3Q19 5^3 {prec} at rest: max|z| {zmax:.2f} rms {zrms:.2f}")
+    assert zmax < 4.5 and zrms < 1.6
