@@ -224,6 +224,30 @@ def run_serving(F, torch, nreq: int = 40, rate: float = 50.0, chunk: int = 100,
     return out
 
 
+def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256):
+    """The D3Q19 generalisation: an n^3 FP32-shifted lattice in the local
+    f-norm basis (u0 = (0.1, 0, 0), kT = 1e-4, tau = 1), no sampling."""
+    p = F.make_params3(n, n, n, precision=F.FP32_SHIFTED, ux0=0.1, kT=1e-4, seed=1)
+    L = F.Lattice3(p, stream=torch.cuda.current_stream())
+    L.step(warmup)
+    L.sync()
+    L.profile(True)
+    L.kernel_time()
+    t0 = time.perf_counter()
+    L.step(steps)
+    L.sync()
+    dt = time.perf_counter() - t0
+    kms, launches = L.kernel_time()
+    sites = n ** 3
+    kernel_ms = kms / max(launches, 1)
+    achieved = 152 * sites / (kernel_ms * 1e-3) / 1e9
+    return {"mlups": sites * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps,
+            "kernel_ms": kernel_ms, "sites": sites, "steps": steps,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "bytes_per_site": 152, "kernel": "step3_kernel<float,float,fnorm>"}}
+
+
 def copy_calibration(reps: int = 5):
     """A plain copy kernel of known size: each launch reads and writes
     exactly 1 GiB.  Its FETCH_SIZE / WRITE_SIZE readings scale the step
@@ -244,7 +268,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "ensemble", "serve", "paper"])
+                    choices=["large", "ensemble", "serve", "paper", "d3q19"])
     ap.add_argument("--requests", type=int, default=None,
                     help="serving window (default 40 in the main line, 400 with --workload serve)")
     ap.add_argument("--no-serving", action="store_true")
@@ -276,6 +300,11 @@ def main():
     if args.workload == "ensemble":
         r = run_ensemble(F, torch, args.steps, args.warmup)
         print(json.dumps({"workload": "64 x 128^2 FP32 ensemble, hipGraph", **r}), flush=True)
+        return
+    if args.workload == "d3q19":
+        r = run_d3q19(F, torch, args.steps, args.warmup)
+        print(json.dumps({"workload": "256^3 D3Q19 FP32-shifted, f-norm, u_x0=0.1, kT=1e-4, "
+                                      "tau=1", **r}), flush=True)
         return
     if args.workload == "paper":
         from paper_1204_6734_amd import analysis as A
