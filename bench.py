@@ -325,6 +325,9 @@ def main():
     bps = BYTES_PER_SITE[r["dtype"]]
     achieved = bps * r["sites"] / (r["kernel_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profiles(r["kernel_name"])
+    # the same traffic with no arithmetic: the practical ceiling on this device
+    copy_ms = F.copy_probe(9, r["sites"], reps=20)
+    copy_gbps = bps * r["sites"] / (copy_ms * 1e-3) / 1e9
     out = {
         "metric": "fluct. D2Q9 MLUPS, % of HBM roofline; served solves/s + p99 latency",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -335,7 +338,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "step_kernel<float,float,fnorm>",
                      "bytes_per_site": bps, "kernel_ms": round(r["kernel_ms"], 4),
-                     "launches": r["launches"]},
+                     "launches": r["launches"],
+                     "copy_probe": {"GBps": round(copy_gbps, 1), "ms": round(copy_ms, 4),
+                                    "frac_of_peak": round(copy_gbps / HBM_PEAK_GBS, 4),
+                                    "kernel_frac_of_copy": round(achieved / copy_gbps, 4)}},
         "pct_hbm_roofline": round(100 * mlups * 1e6 * bps / (HBM_PEAK_GBS * 1e9), 2),
         "launch": r["launch"],
     }

@@ -186,6 +186,17 @@ void flb_lattice_destroy(flb_lattice* L);
 /* Message of the last failed call on this thread (never NULL). */
 const char* flb_last_error(void);
 
+/* Measurement utility, not part of the method: the device time of one copy
+ * of nplanes (1..32) planes of plane_elems (< 2^32) 4-byte elements into a
+ * second set of planes, with the step kernel's memory shape (each thread
+ * reads one element of every plane, then writes them; coalesced, 256-thread
+ * workgroups) and no arithmetic, averaged over reps (1..1000) copies after
+ * three unmeasured ones.  The practical bandwidth ceiling of the step
+ * kernel's traffic on the current device is 2 nplanes plane_elems 4 bytes
+ * over that time.  Allocates and frees two buffers of nplanes plane_elems
+ * 4 bytes on the current device; synchronises the device's null stream. */
+int flb_copy_probe(int32_t nplanes, uint64_t plane_elems, int32_t reps, double* ms_per_copy);
+
 /* ------------------------------------------------------------- ensembles
  * n replicas of one lattice shape (same nx, ny, precision, basis), each with
  * its own rho0, u0, kT, tau, seed and sampling, advanced by one batched

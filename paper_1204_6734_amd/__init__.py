@@ -144,6 +144,7 @@ _SIGS = {
     "flb3_lattice_reset_stats": [C.c_void_p],
     "flb3_lattice_profile": [C.c_void_p, C.c_int32],
     "flb3_lattice_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
+    "flb_copy_probe": [C.c_int32, C.c_uint64, C.c_int32, C.POINTER(C.c_double)],
     "flb_server_create": [C.POINTER(ServerConfig), C.c_void_p, C.POINTER(C.c_void_p)],
     "flb_server_submit": [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)],
     "flb_server_pump": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
@@ -433,6 +434,14 @@ class Ensemble(_Tunable):
         n = C.c_uint64()
         _check(load().flb_ensemble_kernel_time(self.h, C.byref(ms), C.byref(n)), "kernel_time")
         return ms.value, n.value
+
+
+def copy_probe(nplanes: int, plane_elems: int, reps: int = 20) -> float:
+    """Device time (ms) of one copy with the step kernel's memory shape and no
+    arithmetic (flb_copy_probe): the practical bandwidth ceiling."""
+    ms = C.c_double()
+    _check(load().flb_copy_probe(nplanes, plane_elems, reps, C.byref(ms)), "copy_probe")
+    return ms.value
 
 
 def make_params3(nx, ny, nz, rho0=1.0, ux0=0.0, uy0=0.0, uz0=0.0, kT=0.0, tau=(1.0,) * 15,

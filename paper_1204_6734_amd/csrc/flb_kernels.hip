@@ -584,6 +584,31 @@ hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------- bandwidth probe
+// A copy with the step kernel's memory shape and none of its arithmetic:
+// every thread moves one 4-byte element of each of nplanes planes (reads
+// of all planes first, then the writes), coalesced, one element per lane.
+__global__ void planes_copy_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                   uint32_t n, int nplanes) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float v[32];
+#pragma unroll
+  for (int p = 0; p < 32; ++p)
+    if (p < nplanes) v[p] = in[(size_t)p * n + i];
+#pragma unroll
+  for (int p = 0; p < 32; ++p)
+    if (p < nplanes) out[(size_t)p * n + i] = v[p];
+}
+
+hipError_t launch_planes_copy(const float* in, float* out, uint32_t n, int nplanes,
+                              hipStream_t st) {
+  if (nplanes < 1 || nplanes > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(planes_copy_kernel, dim3((n + 255) / 256), dim3(256), 0, st, in, out, n,
+                     nplanes);
+  return hipGetLastError();
+}
+
 static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 static int ilog2(int n) {
   int l = 0;

@@ -315,3 +315,44 @@ int finish_covariance(const Stats& S, const std::vector<double>& rec, const doub
 }  // namespace flb
 
 extern "C" const char* flb_last_error(void) { return flb::g_err.c_str(); }
+
+extern "C" int flb_copy_probe(int32_t nplanes, uint64_t plane_elems, int32_t reps,
+                              double* ms_per_copy) {
+  using flb::set_error;
+  if (nplanes < 1 || nplanes > 32 || plane_elems == 0 || plane_elems >= (1ull << 32) ||
+      (uint64_t)nplanes * plane_elems >= (1ull << 40) || reps < 1 || reps > 1000 ||
+      !ms_per_copy)
+    return set_error(FLB_E_ARG, "copy probe: bad arguments");
+  const size_t bytes = (size_t)nplanes * plane_elems * sizeof(float);
+  float *a = nullptr, *b = nullptr;
+  if (hipMalloc((void**)&a, bytes) != hipSuccess) return set_error(FLB_E_OOM, "copy probe");
+  if (hipMalloc((void**)&b, bytes) != hipSuccess) {
+    (void)hipFree(a);
+    return set_error(FLB_E_OOM, "copy probe");
+  }
+  struct Free {
+    float *a, *b;
+    ~Free() {
+      (void)hipFree(a);
+      (void)hipFree(b);
+    }
+  } fr{a, b};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMemset(a, 0, bytes);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const uint32_t n = (uint32_t)plane_elems;
+  for (int w = 0; w < 3 && e == hipSuccess; ++w) e = flb::launch_planes_copy(a, b, n, nplanes, 0);
+  if (e == hipSuccess) e = hipEventRecord(e0, 0);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    e = flb::launch_planes_copy(a, b, n, nplanes, 0);
+  if (e == hipSuccess) e = hipEventRecord(e1, 0);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return flb::hip_fail(e, "copy probe");
+  *ms_per_copy = ms / reps;
+  return FLB_OK;
+}

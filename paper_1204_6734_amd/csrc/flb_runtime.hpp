@@ -66,6 +66,8 @@ hipError_t launch_close_block(double* partials, int ntiles, double* record, hipS
 hipError_t launch_merge_blocks(double* rec, int nhalf, hipStream_t st);
 hipError_t launch_open_sum(const double* partials, int ntiles, double* out, hipStream_t st);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
+hipError_t launch_planes_copy(const float* in, float* out, uint32_t n, int nplanes,
+                              hipStream_t st);
 hipError_t sk_prepare(size_t max_lds);
 hipError_t launch_sk_sample(int storage, void* z, void* zt, double* acc, int nx, int ny,
                             const void* twx, const void* twy, size_t max_lds, hipStream_t st);

@@ -96,3 +96,12 @@ def test_d3q19_struct_layouts_and_argument_errors():
     codes = [lib.flb3_lattice_create(C.byref(p), None, C.byref(h)) for p in bad]
     assert codes[:4] == [F.E_ARG] * 4 and codes[4] == F.E_INVALID_VELOCITY
     assert lib.flb3_lattice_step(None, 1) == F.E_ARG
+
+
+def test_copy_probe_argument_errors():
+    import paper_1204_6734_amd as F
+    lib = F.load()
+    ms = C.c_double()
+    for args in [(0, 1024, 5), (33, 1024, 5), (9, 0, 5), (9, 1 << 32, 5), (9, 1024, 0)]:
+        assert lib.flb_copy_probe(*args, C.byref(ms)) == F.E_ARG
+    assert lib.flb_copy_probe(9, 1024, 5, None) == F.E_ARG

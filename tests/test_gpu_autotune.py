@@ -107,3 +107,10 @@ def test_set_launch_rejects_bad_shapes(flb):
         with pytest.raises(flb.FlbError) as e:
             L.set_launch(tpb, grid)
         assert e.value.code == flb.E_ARG
+
+
+def test_copy_probe_measures_a_copy(flb):
+    ms = flb.copy_probe(9, 1 << 20, reps=5)
+    gbps = 2 * 9 * (1 << 20) * 4 / (ms * 1e-3) / 1e9
+    print(f"9-plane copy of 2^20 elements: {ms:.4f} ms, {gbps:.0f} GB/s")
+    assert 0 < ms < 100 and gbps > 100
