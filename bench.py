@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"f32": 72, "f64": 144}
 # sources of the step kernel (the one whose HBM traffic the profiles record)
 KERNEL_SOURCES = ["paper_1204_6734_amd/csrc/flb_device.hpp",
+                  "paper_1204_6734_amd/csrc/flb_buffer.hpp",
                   "paper_1204_6734_amd/csrc/flb_step.hip",
                   "paper_1204_6734_amd/csrc/flb_kernels.hpp"]
 

@@ -109,9 +109,15 @@ struct Lattice3 {
     h.u0[0] = p.ux0;
     h.u0[1] = p.uy0;
     h.u0[2] = p.uz0;
+    h.rho0f = (float)p.rho0;
+    for (int a = 0; a < 3; ++a) h.u0f[a] = (float)h.u0[a];
     for (int a = 0; a < 15; ++a) {
       h.rt[a] = 1.0 / p.tau[a];
       h.xc[a] = std::sqrt(mu * (2 * p.tau[a] - 1)) / p.tau[a];
+      h.keep[a] = 1.0 - h.rt[a];
+      h.rtf[a] = (float)h.rt[a];
+      h.xcf[a] = (float)h.xc[a];
+      h.keepf[a] = (float)h.keep[a];
     }
     for (int i = 0; i < 19; ++i) h.shift[i] = equilibrium3(i, p.rho0, h.u0);
     // one allocation: descriptor, clock, error flags, populations, partials,

@@ -15,6 +15,7 @@
 #include <stdint.h>
 
 #include "d3q19_tables.hpp"
+#include "flb_buffer.hpp"
 #include "flb_d3q19.hpp"
 #include "flb_device.hpp"
 
@@ -26,7 +27,7 @@ constexpr double kS3 = 1.7320508075688772935;
 template <typename R>
 struct Const3 {
   R rho0, u0[3];
-  R rt[15], xc[15];
+  R rt[15], xc[15], keep[15];  // 1/tau, xi / sqrt(rho), 1 - 1/tau
 };
 
 template <typename R>
@@ -34,11 +35,12 @@ __device__ __forceinline__ Const3<R> const3(const Desc3& d);
 template <>
 __device__ __forceinline__ Const3<float> const3<float>(const Desc3& d) {
   Const3<float> c;
-  c.rho0 = (float)d.rho0;
-  for (int a = 0; a < 3; ++a) c.u0[a] = (float)d.u0[a];
+  c.rho0 = d.rho0f;
+  for (int a = 0; a < 3; ++a) c.u0[a] = d.u0f[a];
   for (int a = 0; a < 15; ++a) {
-    c.rt[a] = (float)d.rt[a];
-    c.xc[a] = (float)d.xc[a];
+    c.rt[a] = d.rtf[a];
+    c.xc[a] = d.xcf[a];
+    c.keep[a] = d.keepf[a];
   }
   return c;
 }
@@ -50,6 +52,7 @@ __device__ __forceinline__ Const3<double> const3<double>(const Desc3& d) {
   for (int a = 0; a < 15; ++a) {
     c.rt[a] = d.rt[a];
     c.xc[a] = d.xc[a];
+    c.keep[a] = d.keep[a];
   }
   return c;
 }
@@ -76,10 +79,12 @@ __device__ __forceinline__ void gaussians15(uint32_t k0, uint32_t k1, uint32_t s
   }
 }
 
-// One collision on shifted populations h (in place); returns error bits.
-template <typename R, int BASIS>
-__device__ __forceinline__ int collide3(R h[19], const Const3<R>& C, uint32_t k0, uint32_t k1,
-                                        int noise, uint32_t site, uint64_t t) {
+// The collision in the fixed Hermite-type rows with n = w m (BASIS 1), on
+// shifted populations h in place; returns error bits (h unchanged on error).
+template <typename R>
+__device__ __forceinline__ int collide3_hermite(R h[19], const Const3<R>& C, uint32_t k0,
+                                                uint32_t k1, int noise, uint32_t site,
+                                                uint64_t t) {
   // moments of h in the basis rows (h = f - f^0(rho0, u0))
   R M[19];
 #pragma unroll
@@ -128,123 +133,195 @@ __device__ __forceinline__ int collide3(R h[19], const Const3<R>& C, uint32_t k0
   for (int a = 0; a < 15; ++a) N[a] = R(0);
   if (noise) gaussians15<R>(k0, k1, site, t, rho, N);
 
-  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  if (BASIS == 1) {
-    // Hermite-type rows with n = w m: relax d directly
-    R Y[15];
+  // Hermite-type rows with n = w m: relax d directly
+  R Y[15];
 #pragma unroll
-    for (int a = 0; a < 15; ++a) Y[a] = C.xc[a] * N[a] - C.rt[a] * d[a];
+  for (int a = 0; a < 15; ++a) Y[a] = C.xc[a] * N[a] - C.rt[a] * d[a];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      R s = R(0);
+  for (int i = 0; i < 19; ++i) {
+    R s = R(0);
 #pragma unroll
-      for (int b = 4; b < 19; ++b)
-        if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * Y[b - 4];
-      h[i] += R(kW3[i]) * s;
-    }
-    return 0;
+    for (int b = 4; b < 19; ++b)
+      if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * Y[b - 4];
+    h[i] += R(kW3[i]) * s;
   }
+  return 0;
+}
 
-  // g_i = f_i^0(1, u) and the validity of the f-norm
-  R g[19];
+constexpr int kBlock3 = 256;   // threads per workgroup (one 64 x 4 tile)
+constexpr int kParkRows = 8;   // rows 1..8 of the Cholesky factor kept in LDS
+constexpr int kPark = kParkRows * (kParkRows + 1) / 2;  // values per thread
+
+// The f-norm collision (BASIS 0) arranged for few live registers, so that
+// several wavefronts share a SIMD: the post-collision state is rebuilt from
+// the basis expansion of eqs. (17)-(18) and (32) instead of being added to
+// the loaded one,
+//   f*_i = rho g_i + sum_{a >= 4} n~^a_i M~*^a,  M~*^a = (1 - 1/tau^a) M~^a + xi^a N^a,
+// (the momentum modes sqrt3 (v - u) have zero moments), so neither h nor g
+// nor the projections P stay live across the factorisation; the Schur
+// complement is formed one column at a time inside the Cholesky sweep, and
+// the Gaussians are drawn only after the forward solve.  In shifted
+// variables, rho g_i - f_i^0(rho0, u0) = drho g_i + rho0 (g_i(u) - g_i(u0)),
+// with the second difference formed from du.  Returns error bits; the code
+// has no branch on them (a divergent exit would keep the failing lanes'
+// inputs live through everything after it), and hout is meaningless where
+// they are set.
+template <typename R>
+__device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C, uint32_t k0,
+                                              uint32_t k1, int noise, uint32_t site, uint64_t t,
+                                              R* __restrict__ park, R hout[19]) {
+  R M[19];
+#pragma unroll
+  for (int b = 0; b < 19; ++b) {
+    R s = R(0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+      if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * h[i];
+    M[b] = s;
+  }
+  const R drho = M[0];
+  const R rho = C.rho0 + drho;
+  const R rs3 = R(1.0 / kS3);
+  R du[3], u[3], su[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    du[a] = (M[1 + a] * rs3 - drho * C.u0[a]) * rcp_t(rho);
+    u[a] = C.u0[a] + du[a];
+    su[a] = u[a] + C.u0[a];
+  }
+  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   R gmin = R(1);
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const R cu = R(kC3[i][0]) * u[0] + R(kC3[i][1]) * u[1] + R(kC3[i][2]) * u[2];
-    g[i] = R(kW3[i]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
-    gmin = fmin(gmin, g[i]);
+    gmin = fmin(gmin, R(kW3[i]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
   }
+  if (!(rho > R(0)) || !(du[0] == du[0]) || !(du[1] == du[1]) || !(du[2] == du[2]))
+    return kErrNonFinite;
   if (!(gmin > R(0))) return kErrInvalidVelocity;
+  const int err = 0;
 
-  // projections of rows 4..18 on the conserved f-norm rows 1, sqrt3 (v_a - u_a)
-  R P0[15], P[3][15];
+  // the Gaussians first: they are consumed column by column below
+  R N[15];
+#pragma unroll
+  for (int a = 0; a < 15; ++a) N[a] = R(0);
+  if (noise) gaussians15<R>(k0, k1, site, t, rho, N);
+
+  const R mono[9] = {u[0], u[1], u[2], u[0] * u[0], u[1] * u[1], u[2] * u[2],
+                     u[0] * u[1], u[0] * u[2], u[1] * u[2]};
+  const R dmono[9] = {du[0], du[1], du[2], du[0] * su[0], du[1] * su[1], du[2] * su[2],
+                      du[0] * u[1] + C.u0[0] * du[1], du[0] * u[2] + C.u0[0] * du[2],
+                      du[1] * u[2] + C.u0[1] * du[2]};
+  // non-equilibrium moments d_b = M_b(f) - M_b(f^0(rho, u)), b = 4..18, and
+  // the projections of rows 4..18 on the conserved rows 1, sqrt3 (v_a - u_a)
+  R d[15], P0[15], P[3][15];
 #pragma unroll
   for (int b = 4; b < 19; ++b) {
-    R g0 = R(0);
+    R pi = R(0), dpi = R(0);
 #pragma unroll
     for (int k = 0; k < 9; ++k)
-      if (kPi3[b][k] != 0.0) g0 += R(kPi3[b][k]) * mono[k];
-    P0[b - 4] = g0;
+      if (kPi3[b][k] != 0.0) {
+        pi += R(kPi3[b][k]) * mono[k];
+        dpi += R(kPi3[b][k]) * dmono[k];
+      }
+    d[b - 4] = M[b] - (drho * pi + C.rho0 * dpi);
+    P0[b - 4] = pi;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       R ga = R(0);
 #pragma unroll
       for (int k = 0; k < 9; ++k)
         if (kG3[1 + a][b][k] != 0.0) ga += R(kG3[1 + a][b][k]) * mono[k];
-      P[a][b - 4] = ga - R(kS3) * u[a] * g0;
+      P[a][b - 4] = ga - R(kS3) * u[a] * pi;
     }
   }
-  // Schur complement of the Gram matrix (lower part, row-major packed),
-  // factorised in place: L[i][j] (j < i) and inverse pivots r[i]
-  R L[120];
-#pragma unroll
-  for (int a = 0; a < 15; ++a)
-#pragma unroll
-    for (int b = 0; b <= a; ++b) {
-      R G = a == b ? R(1) - R(1.5) * uu : R(0);
-#pragma unroll
-      for (int k = 0; k < 9; ++k)
-        if (kG3[4 + a][4 + b][k] != 0.0) G += R(kG3[4 + a][4 + b][k]) * mono[k];
-      G -= P0[a] * P0[b] + P[0][a] * P[0][b] + P[1][a] * P[1][b] + P[2][a] * P[2][b];
-      L[a * (a + 1) / 2 + b] = G;
-    }
-  R r[15];
+  // Cholesky factor of the Schur complement G' = <m^a, m^b>_g - P0 P0^T -
+  // sum_a P_a P_a^T (packed lower part L[i(i+1)/2 + j], inverse pivots r),
+  // one column at a time; each column also takes its step of the forward
+  // solve M~ = L^-1 d in column form (d_i -= L_ij M~_j for i > j), after
+  // which M~_j is relaxed at once: x_j = M~*_j = (1 - 1/tau_j) M~_j + xi_j N_j
+  R L[120], r[15], x[15];
 #pragma unroll
   for (int j = 0; j < 15; ++j) {
-    R dj = L[j * (j + 1) / 2 + j];
 #pragma unroll
-    for (int k = 0; k < j; ++k) dj -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
-    r[j] = rsqrt_t(dj);
+    for (int i = j; i < 15; ++i) {
+      R G = i == j ? R(1) - R(1.5) * uu : R(0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if (kG3[4 + i][4 + j][k] != 0.0) G += R(kG3[4 + i][4 + j][k]) * mono[k];
+      G -= P0[i] * P0[j] + P[0][i] * P[0][j] + P[1][i] * P[1][j] + P[2][i] * P[2][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) G -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+      L[i * (i + 1) / 2 + j] = G;
+    }
+    r[j] = rsqrt_t(L[j * (j + 1) / 2 + j]);
+    const R mj = d[j] * r[j];
 #pragma unroll
     for (int i = j + 1; i < 15; ++i) {
-      R s = L[i * (i + 1) / 2 + j];
+      L[i * (i + 1) / 2 + j] *= r[j];
+      d[i] -= L[i * (i + 1) / 2 + j] * mj;
+    }
+    x[j] = C.keep[j] * mj + C.xc[j] * N[j];
+    // row j is now needed only by the back substitution: rows 1..kParkRows
+    // wait for it in LDS (one value per thread, stride one workgroup)
+    if (j >= 1 && j <= kParkRows) {
 #pragma unroll
-      for (int k = 0; k < j; ++k) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
-      L[i * (i + 1) / 2 + j] = s * r[j];
+      for (int k = 0; k < j; ++k) park[(j * (j - 1) / 2 + k) * kBlock3] = L[j * (j + 1) / 2 + k];
     }
   }
-  // M~ = L^-1 d, relaxation and noise, y = L^-T dM~
-  R x[15];
-#pragma unroll
-  for (int i = 0; i < 15; ++i) {
-    R s = d[i];
-#pragma unroll
-    for (int k = 0; k < i; ++k) s -= L[i * (i + 1) / 2 + k] * x[k];
-    x[i] = s * r[i];
-  }
-#pragma unroll
-  for (int i = 0; i < 15; ++i) x[i] = C.xc[i] * N[i] - C.rt[i] * x[i];
+  asm volatile("" ::: "memory");  // the parked rows are read back from LDS
+  // y = L^-T M~*, by rows of L from the last (x_i -= L_ki y_k for i < k)
   R y[15];
 #pragma unroll
-  for (int i = 14; i >= 0; --i) {
-    R s = x[i];
+  for (int k = 14; k >= 0; --k) {
+    y[k] = x[k] * r[k];
 #pragma unroll
-    for (int k = i + 1; k < 15; ++k) s -= L[k * (k + 1) / 2 + i] * y[k];
-    y[i] = s * r[i];
+    for (int i = 0; i < k; ++i) {
+      const R l = k <= kParkRows ? park[(k * (k - 1) / 2 + i) * kBlock3] : L[k * (k + 1) / 2 + i];
+      x[i] -= l * y[k];
+    }
   }
-  // df_i = g_i [ sum_b m_i^b y_b - A0 - sum_a m~^a_i A_a ],
-  // m~^a_i = sqrt3 (c_ia - u_a): = g_i [ sigma_i + K - sum_a c_ia B_a ]
-  R A0 = R(0), A[3] = {R(0), R(0), R(0)};
-#pragma unroll
-  for (int b = 0; b < 15; ++b) {
-    A0 += P0[b] * y[b];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) A[a] += P[a][b] * y[b];
-  }
-  const R K = R(kS3) * (u[0] * A[0] + u[1] * A[1] + u[2] * A[2]) - A0;
-  const R B[3] = {R(kS3) * A[0], R(kS3) * A[1], R(kS3) * A[2]};
+  // sum_a n~^a_i M~*^a = g_i [sigma_i - A0 - sum_a m~^a_i A_a] with
+  // sigma_i = sum_b m^b_i y_b, A0 = <1, sigma>_g, A_a = <m~^a, sigma>_g, and
+  // m~^a_i = sqrt3 (c_ia - u_a): = g_i [sigma_i + K - sum_a c_ia B_a]
+  R sg[19], g[19];
+  R A0 = R(0), Cg[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    R s = K;
+    const R cu = R(kC3[i][0]) * u[0] + R(kC3[i][1]) * u[1] + R(kC3[i][2]) * u[2];
+    g[i] = R(kW3[i]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+    R s = R(0);
 #pragma unroll
     for (int b = 4; b < 19; ++b)
       if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * y[b - 4];
+    sg[i] = s;
+    const R gs = g[i] * s;
+    A0 += gs;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-      if (kC3[i][a] != 0) s -= R(kC3[i][a]) * B[a];
-    h[i] += g[i] * s;
+    for (int a = 0; a < 3; ++a) {
+      if (kC3[i][a] > 0) Cg[a] += gs;
+      if (kC3[i][a] < 0) Cg[a] -= gs;
+    }
   }
-  return 0;
+  R B[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) B[a] = R(3) * (Cg[a] - u[a] * A0);
+  const R K = u[0] * B[0] + u[1] * B[1] + u[2] * B[2] - A0 + drho;
+  const R dusu = du[0] * su[0] + du[1] * su[1] + du[2] * su[2];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    R s = sg[i] + K;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (kC3[i][a] > 0) s -= B[a];
+      if (kC3[i][a] < 0) s += B[a];
+    }
+    const R cdu = R(kC3[i][0]) * du[0] + R(kC3[i][1]) * du[1] + R(kC3[i][2]) * du[2];
+    const R csu = R(kC3[i][0]) * su[0] + R(kC3[i][1]) * su[1] + R(kC3[i][2]) * su[2];
+    const R dg = R(kW3[i]) * (R(3) * cdu + R(4.5) * cdu * csu - R(1.5) * dusu);
+    hout[i] = g[i] * s + C.rho0 * dg;
+  }
+  return err;
 }
 
 // --------------------------------------------------------------- kernels
@@ -326,39 +403,58 @@ __device__ __forceinline__ uint32_t cell(int x, int y, int z, const Desc3& d) {
   return ((uint32_t)z * d.ny + y) * d.nx + x;
 }
 
-// Element of the population array a site reads in phase ODD for direction
-// i: even phase plane i at the site; odd phase plane opp(i) at x - c_i.
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// Wavefronts per SIMD the register allocation of a step variant aims at.
+template <typename R, int BASIS, bool SAMPLE>
+constexpr int waves3() {
+  return sizeof(R) == 8 ? 1 : 2;
+}
+
+// One 64 x 4 tile of one z plane per workgroup, one wavefront per tile row,
+// so y and z are wave-uniform: a site reads (and writes back) plane i at
+// itself in the even phase, plane opp(i) at x - c_i in the odd phase.  The
+// per-lane part of an offset is one of three columns x - 1, x, x + 1; the
+// row part (nine distinct (y, z) shifts) is scalar.  Tiles are renumbered
+// so that each XCD sweeps a contiguous range of z planes.
 template <typename S, typename R, int BASIS, bool SAMPLE, int ODD>
-__global__ __launch_bounds__(256) void step3_kernel(const Desc3* __restrict__ desc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves3<R, BASIS, SAMPLE>())))
+void step3_kernel(const Desc3* __restrict__ desc,
                                                     const uint64_t* __restrict__ clock,
                                                     uint32_t step_idx) {
   const Desc3& d = *desc;
   const uint64_t t = *clock + step_idx;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int z = tile / d.tiles_xy;
-  const int r = tile - z * d.tiles_xy;
-  const int ty = r / d.tiles_x, tx = r - ty * d.tiles_x;
+  const int rr = tile - z * d.tiles_xy;
+  const int ty = rr / d.tiles_x, tx = rr - ty * d.tiles_x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = tx * 64 + (threadIdx.x & 63), y = ty * 4 + wave;
   const bool active = x < d.nx && y < d.ny;
   const uint32_t N = (uint32_t)d.nx * d.ny * d.nz;
-  S* pop = reinterpret_cast<S*>(d.pop);
-  uint32_t idx[19];
+  constexpr uint32_t E = sizeof(S);
+  const uint32_t xc = (uint32_t)x * E;
+  uint32_t xm = xc - E, xp = xc + E;
+  if (ODD && (tx == 0 || tx == d.tiles_x - 1)) {
+    // wave-uniform: only the wavefronts at the two ends of a row wrap
+    asm volatile("" : "+v"(xm), "+v"(xp));
+    xm = x == 0 ? (uint32_t)(d.nx - 1) * E : xm;
+    xp = x == d.nx - 1 ? 0u : xp;
+  }
+  uint32_t voff[19], soff[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int cx = ODD ? kC3[i][0] : 0, cy = ODD ? kC3[i][1] : 0, cz = ODD ? kC3[i][2] : 0;
+    voff[i] = cx > 0 ? xm : (cx < 0 ? xp : xc);
+    const int ys = cy == 0 ? y : wrap(y - cy, d.ny), zs = cz == 0 ? z : wrap(z - cz, d.nz);
+    soff[i] = ((uint32_t)zs * d.ny + (uint32_t)ys) * (uint32_t)d.nx * E;
+  }
   R h[19];
   if (active) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      if (!ODD) {
-        idx[i] = (uint32_t)i * N + cell(x, y, z, d);
-      } else {
-        const int xs = wrap(x - kC3[i][0], d.nx), ys = wrap(y - kC3[i][1], d.ny);
-        const int zs = wrap(z - kC3[i][2], d.nz);
-        idx[i] = (uint32_t)kOpp3[i] * N + cell(xs, ys, zs, d);
-      }
-      h[i] = (R)pop[idx[i]];
-    }
+    for (int i = 0; i < 19; ++i)
+      h[i] = (R)buf_load(plane_rsrc<S>(d.pop, N, ODD ? kOpp3[i] : i), voff[i], soff[i],
+                         (S*)nullptr);
   } else {
 #pragma unroll
     for (int i = 0; i < 19; ++i) h[i] = R(0);
@@ -369,15 +465,43 @@ __global__ __launch_bounds__(256) void step3_kernel(const Desc3* __restrict__ de
   }
   if (!active) return;
   const Const3<R> C = const3<R>(d);
-  const int e = collide3<R, BASIS>(h, C, d.k0, d.k1, d.noise, cell(x, y, z, d), t);
+  const uint32_t site = cell(x, y, z, d);
+  __shared__ R park[BASIS == 0 ? kPark : 1][kBlock3];
+  R hn[19];
+  int e;
+  if constexpr (BASIS == 0) {
+    e = collide3_fnorm<R>(h, C, d.k0, d.k1, d.noise, site, t, &park[0][threadIdx.x], hn);
+  } else {
+    e = collide3_hermite<R>(h, C, d.k0, d.k1, d.noise, site, t);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) hn[i] = h[i];
+  }
   if (e) {
+    // the lattice records the error and its step
     atomicOr(d.err, e);
     atomicMin(d.err_step, (unsigned long long)t);
-    return;
   }
-  // the post-collision value of direction opp(i) goes back to idx[i]
+  // the plane resources are formed again for the stores from an opaque copy
+  // of the base, so their SGPRs are not held through the collision
+  void* pop_late = d.pop;
+  asm volatile("" : "+s"(pop_late));
+  if constexpr (BASIS == 0) {
+    if (__builtin_amdgcn_ballot_w64(e != 0)) {
+      // a site of this wavefront failed (rare): it streams uncollided, with
+      // its values read again (nothing of this step is stored yet); the
+      // branch is wave-uniform, so the buffer resources stay scalar
 #pragma unroll
-  for (int i = 0; i < 19; ++i) pop[idx[i]] = (S)h[kOpp3[i]];
+      for (int i = 0; i < 19; ++i) {
+        const R v = (R)buf_load(plane_rsrc<S>(pop_late, N, ODD ? kOpp3[i] : i), voff[i], soff[i],
+                                (S*)nullptr);
+        hn[i] = e ? v : hn[i];
+      }
+    }
+  }
+  // the post-collision value of direction opp(i) goes back where i was read
+#pragma unroll
+  for (int i = 0; i < 19; ++i)
+    buf_store(plane_rsrc<S>(pop_late, N, ODD ? kOpp3[i] : i), voff[i], soff[i], (S)hn[kOpp3[i]]);
 }
 
 // State I/O: f (unshifted FP64, [19][nz][ny][nx]) <-> storage at phase odd

@@ -26,15 +26,11 @@
 
 #include <algorithm>
 
+#include "flb_buffer.hpp"
 #include "flb_device.hpp"
 #include "flb_kernels.hpp"
 
 namespace flb {
-
-__device__ __forceinline__ int xcd_tile(int bid, int nb) {
-  const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
-  return xcd * q + (xcd < r ? xcd : r) + (bid >> 3);
-}
 
 __device__ __forceinline__ int find_slot(const int* __restrict__ prefix, int nslots, int tile) {
   int lo = 0, hi = nslots;
@@ -196,34 +192,6 @@ __device__ __forceinline__ void site_offsets(int x, int y, int nx, int ny, bool 
     voff[7] = xp; soff[7] = rp;  // v=(-1,-1) from (x+1, y+1)
     voff[8] = xm; soff[8] = rp;  // v=( 1,-1) from (x-1, y+1)
   }
-}
-
-// Raw buffer access to one population plane: the 128-bit resource (base,
-// size) is wave-uniform and lives in SGPRs, the per-lane byte offset is a
-// 32-bit VGPR, so no per-lane 64-bit address arithmetic is needed.  An
-// offset outside the plane reads zero and drops the store.
-template <typename S>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(void* pop, uint32_t N, int k) {
-  char* base = reinterpret_cast<char*>(pop) + (size_t)k * N * sizeof(S);
-  return __builtin_amdgcn_make_buffer_rsrc(base, 0, N * (uint32_t)sizeof(S), 0x00020000);
-}
-
-__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                          uint32_t soff, float*) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                           uint32_t soff, double*) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                          float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
-}
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                          double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
 // One tile (or none: tile < 0) of the batched step.  A tile of a slot whose
