@@ -153,19 +153,21 @@ constexpr int kParkRows = 8;   // rows 1..8 of the Cholesky factor kept in LDS
 constexpr int kPark = kParkRows * (kParkRows + 1) / 2;  // values per thread
 
 // The f-norm collision (BASIS 0) arranged for few live registers, so that
-// several wavefronts share a SIMD: the post-collision state is rebuilt from
-// the basis expansion of eqs. (17)-(18) and (32) instead of being added to
-// the loaded one,
+// two wavefronts share a SIMD: the post-collision state is rebuilt from the
+// basis expansion of eqs. (17)-(18) and (32) instead of being added to the
+// loaded one,
 //   f*_i = rho g_i + sum_{a >= 4} n~^a_i M~*^a,  M~*^a = (1 - 1/tau^a) M~^a + xi^a N^a,
 // (the momentum modes sqrt3 (v - u) have zero moments), so neither h nor g
-// nor the projections P stay live across the factorisation; the Schur
-// complement is formed one column at a time inside the Cholesky sweep, and
-// the Gaussians are drawn only after the forward solve.  In shifted
-// variables, rho g_i - f_i^0(rho0, u0) = drho g_i + rho0 (g_i(u) - g_i(u0)),
-// with the second difference formed from du.  Returns error bits; the code
-// has no branch on them (a divergent exit would keep the failing lanes'
-// inputs live through everything after it), and hout is meaningless where
-// they are set.
+// nor the projections P stay live across the factorisation.  The Gaussians
+// are drawn first and consumed column by column; the Schur complement is
+// formed one column at a time inside the Cholesky sweep, which also takes
+// the forward solve in column form; rows of the factor that only the back
+// substitution still needs wait in LDS (`park`, this thread's slot of a
+// [kPark][kBlock3] array).  In shifted variables, rho g_i - f_i^0(rho0, u0)
+// = drho g_i + rho0 (g_i(u) - g_i(u0)), the second difference formed from
+// du.  Returns error bits; hout is written only on success (on failure the
+// caller reads the site's values again, so nothing of the input has to stay
+// live for the failing lanes while the others go on).
 template <typename R>
 __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C, uint32_t k0,
                                               uint32_t k1, int noise, uint32_t site, uint64_t t,
@@ -405,8 +407,10 @@ __device__ __forceinline__ uint32_t cell(int x, int y, int z, const Desc3& d) {
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-// Wavefronts per SIMD the register allocation of a step variant aims at.
-template <typename R, int BASIS, bool SAMPLE>
+// Wavefronts per SIMD the register allocation of a step variant aims at:
+// two in FP32 (at three the f-norm collision spills; measured no faster),
+// one in FP64.
+template <typename R>
 constexpr int waves3() {
   return sizeof(R) == 8 ? 1 : 2;
 }
@@ -418,10 +422,9 @@ constexpr int waves3() {
 // row part (nine distinct (y, z) shifts) is scalar.  Tiles are renumbered
 // so that each XCD sweeps a contiguous range of z planes.
 template <typename S, typename R, int BASIS, bool SAMPLE, int ODD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves3<R, BASIS, SAMPLE>())))
-void step3_kernel(const Desc3* __restrict__ desc,
-                                                    const uint64_t* __restrict__ clock,
-                                                    uint32_t step_idx) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves3<R>()))) void
+step3_kernel(const Desc3* __restrict__ desc, const uint64_t* __restrict__ clock,
+             uint32_t step_idx) {
   const Desc3& d = *desc;
   const uint64_t t = *clock + step_idx;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
