@@ -33,6 +33,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"f32": 72, "f64": 144}
+# D3Q19 FP32 f-norm step: VALU wavefront instructions per wavefront (= per
+# site), profiles/step3_fp32_256cube_d3q19.md
+D3Q19_VALU_PER_SITE = 2839
 # sources of the step kernel (the one whose HBM traffic the profiles record)
 KERNEL_SOURCES = ["paper_1204_6734_amd/csrc/flb_device.hpp",
                   "paper_1204_6734_amd/csrc/flb_buffer.hpp",
@@ -242,11 +245,17 @@ def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256):
     sites = n ** 3
     kernel_ms = kms / max(launches, 1)
     achieved = 152 * sites / (kernel_ms * 1e-3) / 1e9
+    # the kernel is bound by VALU issue: wavefront instructions per site from
+    # the SQ_INSTS_VALU / SQ_WAVES counters of the profile summary, at four
+    # cycles per wavefront instruction on 1024 SIMDs at 2.4 GHz
+    issue_ms = D3Q19_VALU_PER_SITE * sites / 64 * 4 / 1024 / 2.4e9 * 1e3
     return {"mlups": sites * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps,
             "kernel_ms": kernel_ms, "sites": sites, "steps": steps,
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "bytes_per_site": 152, "kernel": "step3_kernel<float,float,fnorm>"}}
+                         "bytes_per_site": 152, "kernel": "step3_kernel<float,float,fnorm>"},
+            "valu": {"per_site": D3Q19_VALU_PER_SITE, "issue_bound_ms": round(issue_ms, 4),
+                     "kernel_over_issue_bound": round(kernel_ms / issue_ms, 4)}}
 
 
 def copy_calibration(reps: int = 5):

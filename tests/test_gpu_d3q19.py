@@ -113,3 +113,22 @@ def test_statistics_at_rest_match_closed_form(flb, prec):
     zmax, zrms = np.abs(z).max(), math.sqrt((z ** 2).mean())
     print(f"D3Q19 5^3 {prec} at rest: max|z| {zmax:.2f} rms {zrms:.2f}")
     assert zmax < 4.5 and zrms < 1.6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_invalid_velocity_is_reported(flb, prec):
+    """A site outside the region where the f-norm exists (some g_i <= 0,
+    Fig. 11; here the rest weight at u = (0.9, 0, 0)) sets the lattice's
+    error flag with the first failing step; the launch itself completes."""
+    precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+    nx, ny, nz = 70, 5, 4
+    L = flb.Lattice3(flb.make_params3(nx, ny, nz, precision=precision, kT=1e-4, seed=2))
+    f = perturbed(nx, ny, nz, (0.0, 0.0, 0.0))
+    vx, vy, vz, w = D.velocities()
+    f[:, 2, 3, 66] = [w[i] * (1 + 3 * 0.9 * vx[i] + 4.5 * (0.9 * vx[i]) ** 2 - 1.5 * 0.81)
+                      for i in range(19)]
+    L.set_populations(f, 5)
+    L.step(3)
+    with pytest.raises(flb.FlbError) as e:
+        L.sync()
+    assert e.value.code == flb.E_INVALID_VELOCITY and L.error_step == 5
