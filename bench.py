@@ -64,13 +64,18 @@ def traffic_from_profiles(name: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(seconds: float = 12.0) -> dict:
+# --basis of the large workload: (config name, basis code of the C ABI)
+BASES = {"fnorm": ("fnorm_local", 0), "hermite": ("hermite", 1), "lut": ("fnorm_lut", 2)}
+
+
+def cpu_baseline(seconds: float = 12.0, basis: int = 0) -> dict:
     """FP64 oracle on a bounded sample: a 128 x 128 lattice with the large
-    workload's parameters, stepped until ~`seconds` of CPU time."""
+    workload's parameters (and basis), stepped until ~`seconds` of CPU time."""
     import oracle as O
     from paper_1204_6734_amd import inputs as I
     nx = ny = 128
-    p = O.make_params(nx, ny, rho0=1.0, ux0=0.1, kT=1e-4, seed=1, init=O.INIT_FIELDS)
+    p = O.make_params(nx, ny, rho0=1.0, ux0=0.1, kT=1e-4, seed=1, init=O.INIT_FIELDS,
+                      basis=basis)
     L = O.Lattice(p)
     L.set_fields(*I.shear_wave_fields(nx, ny, ux0=0.1, amp=1e-3))
     L.step(5)
@@ -85,11 +90,13 @@ def cpu_baseline(seconds: float = 12.0) -> dict:
 
 
 def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 100,
-              launch=None):
+              launch=None, basis: str = "fnorm", precision: str = "fp32"):
     from paper_1204_6734_amd import inputs as I
     stream = torch.cuda.current_stream()
-    p = F.make_params(nx, nx, precision=F.FP32_SHIFTED, rho0=1.0, ux0=0.1, kT=1e-4, seed=1,
-                      init=F.INIT_FIELDS, sk_every=every)
+    bname, bcode = BASES[basis]
+    fp32 = precision == "fp32"
+    p = F.make_params(nx, nx, precision=F.FP32_SHIFTED if fp32 else F.FP64, basis=bcode,
+                      rho0=1.0, ux0=0.1, kT=1e-4, seed=1, init=F.INIT_FIELDS, sk_every=every)
     L = F.Lattice(p, stream=stream)
     L.set_fields(*I.shear_wave_fields(nx, nx, ux0=0.1, amp=1e-3))
     if launch is None:
@@ -126,13 +133,17 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
     return {"sites": sites, "dt": dt, "kernel_ms": kms / max(launches, 1), "launches": launches,
             "mode_log": [abs(z) for z in log[-3:]],
             "launch": {"chosen": L.get_launch(), "candidates": tune},
-            "config": {"workload": f"{nx}x{nx} D2Q9 FP32-shifted, rho0=1, u_x0=0.1, kT=1e-4, "
+            "config": {"workload": f"{nx}x{nx} D2Q9 {'FP32-shifted' if fp32 else 'FP64'}, "
+                                   f"{'' if basis == 'fnorm' else bname + ' basis, '}"
+                                   f"rho0=1, u_x0=0.1, kT=1e-4, "
                                    f"tau=1, shear wave 1e-3 sin(2 pi x/L); " +
                                    (f"S(k) and j~_y(2 pi/L) every {every} steps" if every > 0
                                     else "no S(k), no mode log"),
-                       "nx": nx, "ny": nx, "precision": "fp32_shifted", "basis": "fnorm_local",
-                       "sk_every": every, "parallelism": "single GPU"},
-            "dtype": "f32", "kernel_name": f"step_fp32_{nx}"}
+                       "nx": nx, "ny": nx, "precision": "fp32_shifted" if fp32 else "fp64",
+                       "basis": bname, "sk_every": every, "parallelism": "single GPU"},
+            "dtype": "f32" if fp32 else "f64",
+            "kernel_label": f"step_kernel<{'float,float' if fp32 else 'double,double'},{bname}>",
+            "kernel_name": f"step_{precision}_{nx}" + ("" if basis == "fnorm" else f"_{basis}")}
 
 
 def run_ensemble(F, torch, steps: int, warmup: int, n: int = 64, side: int = 128,
@@ -289,6 +300,10 @@ def main():
     ap.add_argument("--launch", default=None,
                     help="TILES,GRID: fix the step launch shape instead of autotuning "
                          "(profiling runs)")
+    ap.add_argument("--basis", default="fnorm", choices=sorted(BASES),
+                    help="collision basis of the large workload (default: the local f-norm)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
+                    help="storage precision of the large workload (default: FP32-shifted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -330,13 +345,14 @@ def main():
         return
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     r = run_large(F, torch, args.steps, args.warmup, nx=args.nx, every=args.sk_every,
-                  launch=launch)
+                  launch=launch, basis=args.basis, precision=args.precision)
     mlups = r["sites"] * args.steps / r["dt"] / 1e6
     bps = BYTES_PER_SITE[r["dtype"]]
     achieved = bps * r["sites"] / (r["kernel_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profiles(r["kernel_name"])
-    # the same traffic with no arithmetic: the practical ceiling on this device
-    copy_ms = F.copy_probe(9, r["sites"], reps=20)
+    # the same traffic with no arithmetic (as many 4-byte planes as the step
+    # reads: 9 in FP32, 18 in FP64): the practical ceiling on this device
+    copy_ms = F.copy_probe(bps // 8, r["sites"], reps=20)
     copy_gbps = bps * r["sites"] / (copy_ms * 1e-3) / 1e9
     out = {
         "metric": "fluct. D2Q9 MLUPS, % of HBM roofline; served solves/s + p99 latency",
@@ -346,7 +362,7 @@ def main():
         "data": "synthetic", "config": r["config"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "step_kernel<float,float,fnorm>",
+                     "traffic": traffic, "kernel": r["kernel_label"],
                      "bytes_per_site": bps, "kernel_ms": round(r["kernel_ms"], 4),
                      "launches": r["launches"],
                      "copy_probe": {"GBps": round(copy_gbps, 1), "ms": round(copy_ms, 4),
@@ -358,7 +374,7 @@ def main():
     if not args.no_serving:
         out["serving"] = run_serving(F, torch, nreq=args.requests or 40)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, BASES[args.basis][1])
     print(json.dumps(out), flush=True)
 
 
