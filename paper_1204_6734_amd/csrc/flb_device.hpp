@@ -114,15 +114,92 @@ __device__ __forceinline__ void box_muller<float, 24>(uint32_t ua, uint32_t ub, 
   box_muller_f32<24>(ua, ub, v, n0, n1);
 }
 
+// FP64 Box-Muller without library calls.  The inputs are integers, which
+// makes exact argument reduction cheap:
+// - ln x for x = (2 ua + 1) 2^-(B+1) in (0, 1): x = 2^e m with m in
+//   [sqrt(1/2), sqrt(2)), ln m = 2 artanh z with z = (m - 1)/(m + 1),
+//   |z| < 0.172, summed as the odd power series to z^21 (the rest is below
+//   2^-56 of the sum), and ln x = e ln 2 + ln m;
+// - the angle theta = 2 pi (ub + 1/2) 2^-B = pi K 2^-B with K = 2 ub + 1:
+//   the octant is K >> (B - 2) and the rest an integer (taken from the
+//   octant's far end in odd octants), so the reduced angle r = pi k 2^-B in
+//   [0, pi/4] carries one rounding; sin r and cos r are their Taylor
+//   polynomials to r^17 and r^18 (the rest is below 1e-19);
+// - the radius sqrt(a) = a rsqrt(a) with the refined reciprocal square root.
+// Each result is within a few ulp of the correctly rounded value.
+__device__ __forceinline__ double rsqrt_t(double x);
+__device__ __forceinline__ double rcp_t(double x);
+
+template <int BITS>
+__device__ __forceinline__ double ln_uniform(uint32_t ua) {
+  const double x = (double)(2u * ua + 1u) * (1.0 / (double)(2ull << BITS));  // exact
+  const double mant = __builtin_amdgcn_frexp_mant(x);  // in [1/2, 1)
+  const int ex = __builtin_amdgcn_frexp_exp(x);
+  const bool low = mant < 0.70710678118654752440;
+  const double m = low ? 2.0 * mant : mant;
+  const int e = low ? ex - 1 : ex;
+  const double z = (m - 1.0) * rcp_t(m + 1.0);
+  const double z2 = z * z;
+  double p = 1.0 / 21.0;
+  p = fma(p, z2, 1.0 / 19.0);
+  p = fma(p, z2, 1.0 / 17.0);
+  p = fma(p, z2, 1.0 / 15.0);
+  p = fma(p, z2, 1.0 / 13.0);
+  p = fma(p, z2, 1.0 / 11.0);
+  p = fma(p, z2, 1.0 / 9.0);
+  p = fma(p, z2, 1.0 / 7.0);
+  p = fma(p, z2, 1.0 / 5.0);
+  p = fma(p, z2, 1.0 / 3.0);
+  p = fma(p, z2, 1.0);
+  return fma((double)e, 0.69314718055994530942, 2.0 * z * p);
+}
+
+template <int BITS>
+__device__ __forceinline__ void sincos_uniform(uint32_t ub, double& sn, double& cs) {
+  const uint32_t K = 2u * ub + 1u;
+  const uint32_t oct = K >> (BITS - 2);
+  const uint32_t rest = K & ((1u << (BITS - 2)) - 1u);
+  const bool odd = (oct & 1u) != 0;
+  const uint32_t k = odd ? (1u << (BITS - 2)) - rest : rest;
+  const double r = (double)k * (3.14159265358979323846 / (double)(1u << BITS));
+  const double r2 = r * r;
+  // factorials to 18! are exact in FP64, so each coefficient is one rounding
+  double ps = 1.0 / 355687428096000.0;           // 1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);      // 1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);          // 1/13!
+  ps = fma(ps, r2, -1.0 / 39916800.0);           // 1/11!
+  ps = fma(ps, r2, 1.0 / 362880.0);              // 1/9!
+  ps = fma(ps, r2, -1.0 / 5040.0);               // 1/7!
+  ps = fma(ps, r2, 1.0 / 120.0);                 // 1/5!
+  ps = fma(ps, r2, -1.0 / 6.0);                  // 1/3!
+  ps = fma(ps, r2, 1.0);
+  double pc = -1.0 / 6402373705728000.0;         // 1/18!
+  pc = fma(pc, r2, 1.0 / 20922789888000.0);      // 1/16!
+  pc = fma(pc, r2, -1.0 / 87178291200.0);        // 1/14!
+  pc = fma(pc, r2, 1.0 / 479001600.0);           // 1/12!
+  pc = fma(pc, r2, -1.0 / 3628800.0);            // 1/10!
+  pc = fma(pc, r2, 1.0 / 40320.0);               // 1/8!
+  pc = fma(pc, r2, -1.0 / 720.0);                // 1/6!
+  pc = fma(pc, r2, 1.0 / 24.0);                  // 1/4!
+  pc = fma(pc, r2, -1.0 / 2.0);                  // 1/2!
+  pc = fma(pc, r2, 1.0);
+  // theta = Q pi/2 + a with a = r (even octant, Q = oct/2) or a = -r (odd
+  // octant, Q = (oct + 1)/2 mod 4); (sin, cos)(Q pi/2 + a) =
+  // (sin a, cos a), (cos a, -sin a), (-sin a, -cos a), (-cos a, sin a)
+  const double sa = odd ? -(r * ps) : r * ps, ca = pc;
+  const uint32_t Q = ((oct + 1u) >> 1) & 3u;
+  const double s0 = (Q & 1u) ? ca : sa, c0 = (Q & 1u) ? sa : ca;
+  sn = Q >= 2u ? -s0 : s0;
+  cs = (Q == 1u || Q == 2u) ? -c0 : c0;
+}
+
 template <int BITS>
 __device__ __forceinline__ void box_muller_f64(uint32_t ua, uint32_t ub, double v, double& n0,
                                                double& n1) {
-  constexpr double scale = 1.0 / (double)(1u << BITS);
-  const double fa = ((double)ua + 0.5) * scale;
-  const double fb = ((double)ub + 0.5) * (2.0 * scale);  // 2u
-  const double r = sqrt((-2.0 * v) * log(fa));
+  const double a = (-2.0 * v) * ln_uniform<BITS>(ua);
+  const double r = a * rsqrt_t(a);
   double s, c;
-  sincospi(fb, &s, &c);
+  sincos_uniform<BITS>(ub, s, c);
   n0 = r * c;
   n1 = r * s;
 }

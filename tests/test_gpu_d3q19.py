@@ -52,6 +52,24 @@ def test_fp64_trajectory_matches_oracle(flb, basis):
         assert err <= 1e-12, (basis, o.t, err)
 
 
+@pytest.mark.parametrize("basis", ["fnorm", "hermite"])
+def test_fp64_noise_matches_oracle(flb, basis):
+    """From equilibrium the first step's change is the noise term alone:
+    f - f^0(rho0, u0) checks the fifteen Gaussians per site to 1e-12
+    relative, at both streaming phases."""
+    b = flb.BASIS_FNORM_LOCAL if basis == "fnorm" else flb.BASIS_HERMITE
+    nx, ny, nz = 70, 5, 4
+    kw = dict(ux0=0.08, uy0=-0.03, uz0=0.02, kT=1e-3, tau=TAUS, seed=23)
+    g, o = both(flb, nx, ny, nz, flb.FP64, b, **kw)
+    f0 = D.equilibrium(1.0, 0.08, -0.03, 0.02)[:, None, None, None]
+    for k in range(2):
+        g.step(1)
+        o.step(1)
+        dg, do = g.populations() - f0, o.populations() - f0
+        err = np.abs(dg - do).max() / np.abs(do).max()
+        assert err <= 1e-12, (basis, k, err)
+
+
 def test_fp32_shifted_matches_fp64_oracle(flb):
     nx, ny, nz = 40, 8, 6
     kw = dict(ux0=0.1, uy0=0.05, uz0=0.0, kT=1e-4, tau=TAUS, seed=3)

@@ -47,6 +47,27 @@ def test_fp64_trajectory_matches_oracle(flb, basis, nx, ny):
     assert g.t == o.t == 1000
 
 
+@pytest.mark.parametrize("basis", ["fnorm", "hermite", "lut"])
+def test_fp64_noise_matches_oracle(flb, basis):
+    """From equilibrium the first step's change is the noise term alone, so
+    comparing f - f^0(rho0, u0) (not f) checks the Gaussians themselves (the
+    log, square root, sine and cosine of the Box-Muller transform, eq. (20)
+    amplitudes) to 1e-12 relative; the second step checks the odd phase.
+    u0 lies away from the midpoints of the table's grid (a velocity exactly
+    half-way between two grid points rounds either way)."""
+    b = BASES[basis][0]
+    nx, ny = 70, 9
+    kw = dict(rho0=1.0, ux0=0.08, uy0=-0.025, kT=1e-3, tau=TAUS, seed=21)
+    g, o = both(flb, nx, ny, flb.FP64, b, **kw)
+    f0 = O.equilibrium(1.0, 0.08, -0.025)[:, None, None]
+    for k in range(2):
+        g.step(1)
+        o.step(1)
+        dg, do = g.populations() - f0, o.populations() - f0
+        err = rel(dg, do)
+        assert err <= 1e-12, (basis, k, err)
+
+
 def test_fp64_moments_match_oracle(flb):
     kw = dict(ux0=0.15, kT=1e-4, tau=TAUS, seed=3)
     g, o = both(flb, 45, 21, flb.FP64, **kw)
