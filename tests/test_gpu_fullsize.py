@@ -28,10 +28,14 @@ def one_step_samples(p_oracle, f_before, t, sites, nx, ny):
     return out
 
 
-def check_sampled(F, prec, nx, ny, ux0, tol, nsample, tau=(1.0,) * 6):
+def check_sampled(F, prec, nx, ny, ux0, tol, nsample, tau=(1.0,) * 6, tune=False):
     kw = dict(ux0=ux0, kT=1e-4, tau=tau, seed=1)
     L = F.Lattice(F.make_params(nx, ny, precision=prec, init=2, **kw))
     L.set_fields(*I.shear_wave_fields(nx, ny, ux0=ux0, amp=1e-3))
+    if tune:
+        # the launch shape the benchmark runs: its autotuner's pick
+        L.autotune(reps=3)
+        print(f"{nx}x{ny}: tuned launch {L.get_launch()}", flush=True)
     po = O.make_params(nx, ny, **kw)
     rng = np.random.default_rng(0)
     sites = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1)]
@@ -51,7 +55,7 @@ def check_sampled(F, prec, nx, ny, ux0, tol, nsample, tau=(1.0,) * 6):
 
 
 def test_8192_fp32_sampled_sites(flb):
-    check_sampled(flb, flb.FP32_SHIFTED, 8192, 8192, 0.1, tol=2e-7, nsample=64)
+    check_sampled(flb, flb.FP32_SHIFTED, 8192, 8192, 0.1, tol=2e-7, nsample=64, tune=True)
 
 
 def test_256_fp64_sampled_sites(flb):
