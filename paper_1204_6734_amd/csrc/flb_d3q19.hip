@@ -79,6 +79,89 @@ __device__ __forceinline__ void gaussians15(uint32_t k0, uint32_t k1, uint32_t s
   }
 }
 
+// Every basis row is even or odd in the velocity (the start polynomials
+// are, and the Gram-Schmidt under the symmetric weights keeps it; the
+// tables are generated exactly so), and opposite velocities are adjacent
+// (2k - 1, 2k), so sums over the nineteen directions fold into sums over
+// the rest velocity and nine pairs.
+constexpr int row_parity(int b) {
+  int par = 0;
+  for (int k = 1; k < 19; k += 2) {
+    if (kM3[b][k] == 0.0 && kM3[b][k + 1] == 0.0) continue;
+    const int p = kM3[b][k] == kM3[b][k + 1] ? 1 : (kM3[b][k] == -kM3[b][k + 1] ? -1 : 2);
+    if (p == 2 || (par != 0 && p != par)) return 2;
+    par = p;
+  }
+  return par == 0 ? 1 : par;
+}
+constexpr bool rows_have_parity() {
+  for (int b = 0; b < 19; ++b) {
+    if (row_parity(b) == 2) return false;
+    if (row_parity(b) == -1 && kM3[b][0] != 0.0) return false;
+  }
+  for (int k = 1; k < 19; k += 2)
+    if (kOpp3[k] != k + 1) return false;
+  return true;
+}
+static_assert(rows_have_parity(), "basis rows must be even or odd, opposite velocities adjacent");
+
+// c_i . v for one of the lattice velocities (components -1, 0, 1).
+template <typename R>
+__device__ __forceinline__ R cdot(int i, const R v[3]) {
+  R s = R(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (kC3[i][a] > 0) s += v[a];
+    if (kC3[i][a] < 0) s -= v[a];
+  }
+  return s;
+}
+
+// M_b = sum_i m^b_i h_i for all nineteen rows.
+template <typename R>
+__device__ __forceinline__ void moments3(const R h[19], R M[19]) {
+  R hs[9], hd[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    hs[k] = h[2 * k + 1] + h[2 * k + 2];
+    hd[k] = h[2 * k + 1] - h[2 * k + 2];
+  }
+#pragma unroll
+  for (int b = 0; b < 19; ++b) {
+    R s = kM3[b][0] != 0.0 ? R(kM3[b][0]) * h[0] : R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      if (kM3[b][2 * k + 1] != 0.0)
+        s = fma(R(kM3[b][2 * k + 1]), row_parity(b) > 0 ? hs[k] : hd[k], s);
+    M[b] = s;
+  }
+}
+
+// sigma_i = sum_{b = 4..18} m^b_i y_{b-4}: the even rows give the part
+// shared by a velocity and its opposite, the odd rows the part that flips.
+template <typename R>
+__device__ __forceinline__ void back3(const R y[15], R sg[19]) {
+  R s0 = R(0);
+#pragma unroll
+  for (int b = 4; b < 19; ++b)
+    if (kM3[b][0] != 0.0) s0 = fma(R(kM3[b][0]), y[b - 4], s0);
+  sg[0] = s0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    R e = R(0), o = R(0);
+#pragma unroll
+    for (int b = 4; b < 19; ++b) {
+      if (kM3[b][2 * k + 1] == 0.0) continue;
+      if (row_parity(b) > 0)
+        e = fma(R(kM3[b][2 * k + 1]), y[b - 4], e);
+      else
+        o = fma(R(kM3[b][2 * k + 1]), y[b - 4], o);
+    }
+    sg[2 * k + 1] = e + o;
+    sg[2 * k + 2] = e - o;
+  }
+}
+
 // The collision in the fixed Hermite-type rows with n = w m (BASIS 1), on
 // shifted populations h in place; returns error bits (h unchanged on error).
 template <typename R>
@@ -87,14 +170,7 @@ __device__ __forceinline__ int collide3_hermite(R h[19], const Const3<R>& C, uin
                                                 uint64_t t) {
   // moments of h in the basis rows (h = f - f^0(rho0, u0))
   R M[19];
-#pragma unroll
-  for (int b = 0; b < 19; ++b) {
-    R s = R(0);
-#pragma unroll
-    for (int i = 0; i < 19; ++i)
-      if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * h[i];
-    M[b] = s;
-  }
+  moments3(h, M);
   const R drho = M[0];
   const R rho = C.rho0 + drho;
   const R rs3 = R(1.0 / kS3);
@@ -137,14 +213,10 @@ __device__ __forceinline__ int collide3_hermite(R h[19], const Const3<R>& C, uin
   R Y[15];
 #pragma unroll
   for (int a = 0; a < 15; ++a) Y[a] = C.xc[a] * N[a] - C.rt[a] * d[a];
+  R sg[19];
+  back3(Y, sg);
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    R s = R(0);
-#pragma unroll
-    for (int b = 4; b < 19; ++b)
-      if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * Y[b - 4];
-    h[i] += R(kW3[i]) * s;
-  }
+  for (int i = 0; i < 19; ++i) h[i] += R(kW3[i]) * sg[i];
   return 0;
 }
 
@@ -173,14 +245,7 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
                                               uint32_t k1, int noise, uint32_t site, uint64_t t,
                                               R* __restrict__ park, R hout[19]) {
   R M[19];
-#pragma unroll
-  for (int b = 0; b < 19; ++b) {
-    R s = R(0);
-#pragma unroll
-    for (int i = 0; i < 19; ++i)
-      if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * h[i];
-    M[b] = s;
-  }
+  moments3(h, M);
   const R drho = M[0];
   const R rho = C.rho0 + drho;
   const R rs3 = R(1.0 / kS3);
@@ -192,11 +257,13 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
     su[a] = u[a] + C.u0[a];
   }
   const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  R gmin = R(1);
+  // g of a velocity pair (c, -c) is w (t +- 3 c.u); the smaller is w (t - |3 c.u|)
+  const R base = R(1) - R(1.5) * uu;
+  R gmin = R(kW3[0]) * base;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const R cu = R(kC3[i][0]) * u[0] + R(kC3[i][1]) * u[1] + R(kC3[i][2]) * u[2];
-    gmin = fmin(gmin, R(kW3[i]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+  for (int k = 1; k < 19; k += 2) {
+    const R cu = cdot<R>(k, u);
+    gmin = fmin(gmin, R(kW3[k]) * ((base + R(4.5) * cu * cu) - fabs(R(3) * cu)));
   }
   if (!(rho > R(0)) || !(du[0] == du[0]) || !(du[1] == du[1]) || !(du[2] == du[2]))
     return kErrNonFinite;
@@ -251,7 +318,9 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
 #pragma unroll
       for (int k = 0; k < 9; ++k)
         if (kG3[4 + i][4 + j][k] != 0.0) G += R(kG3[4 + i][4 + j][k]) * mono[k];
-      G -= P0[i] * P0[j] + P[0][i] * P[0][j] + P[1][i] * P[1][j] + P[2][i] * P[2][j];
+      G = fma(-P0[i], P0[j], G);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) G = fma(-P[c][i], P[c][j], G);
 #pragma unroll
       for (int k = 0; k < j; ++k) G -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
       L[i * (i + 1) / 2 + j] = G;
@@ -287,22 +356,22 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
   // sigma_i = sum_b m^b_i y_b, A0 = <1, sigma>_g, A_a = <m~^a, sigma>_g, and
   // m~^a_i = sqrt3 (c_ia - u_a): = g_i [sigma_i + K - sum_a c_ia B_a]
   R sg[19], g[19];
-  R A0 = R(0), Cg[3] = {R(0), R(0), R(0)};
+  back3(y, sg);
+  g[0] = R(kW3[0]) * base;
+  R A0 = g[0] * sg[0], Cg[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const R cu = R(kC3[i][0]) * u[0] + R(kC3[i][1]) * u[1] + R(kC3[i][2]) * u[2];
-    g[i] = R(kW3[i]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
-    R s = R(0);
-#pragma unroll
-    for (int b = 4; b < 19; ++b)
-      if (kM3[b][i] != 0.0) s += R(kM3[b][i]) * y[b - 4];
-    sg[i] = s;
-    const R gs = g[i] * s;
-    A0 += gs;
+  for (int k = 1; k < 19; k += 2) {
+    const R cu = cdot<R>(k, u);
+    const R t = R(kW3[k]) * (base + R(4.5) * cu * cu), d = R(3 * kW3[k]) * cu;
+    g[k] = t + d;
+    g[k + 1] = t - d;
+    const R gp = g[k] * sg[k], gm = g[k + 1] * sg[k + 1];
+    A0 += gp + gm;
+    const R dl = gp - gm;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (kC3[i][a] > 0) Cg[a] += gs;
-      if (kC3[i][a] < 0) Cg[a] -= gs;
+      if (kC3[k][a] > 0) Cg[a] += dl;
+      if (kC3[k][a] < 0) Cg[a] -= dl;
     }
   }
   R B[3];
@@ -310,18 +379,15 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
   for (int a = 0; a < 3; ++a) B[a] = R(3) * (Cg[a] - u[a] * A0);
   const R K = u[0] * B[0] + u[1] * B[1] + u[2] * B[2] - A0 + drho;
   const R dusu = du[0] * su[0] + du[1] * su[1] + du[2] * su[2];
+  // g_i(u) - g_i(u0) = w_i (3 c.du + 4.5 (c.du)(c.su) - 1.5 du.su): the
+  // first term flips sign between c and -c, the rest does not
+  hout[0] = g[0] * (sg[0] + K) + C.rho0 * (R(kW3[0]) * (R(-1.5) * dusu));
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    R s = sg[i] + K;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (kC3[i][a] > 0) s -= B[a];
-      if (kC3[i][a] < 0) s += B[a];
-    }
-    const R cdu = R(kC3[i][0]) * du[0] + R(kC3[i][1]) * du[1] + R(kC3[i][2]) * du[2];
-    const R csu = R(kC3[i][0]) * su[0] + R(kC3[i][1]) * su[1] + R(kC3[i][2]) * su[2];
-    const R dg = R(kW3[i]) * (R(3) * cdu + R(4.5) * cdu * csu - R(1.5) * dusu);
-    hout[i] = g[i] * s + C.rho0 * dg;
+  for (int k = 1; k < 19; k += 2) {
+    const R cB = cdot<R>(k, B), cdu = cdot<R>(k, du), csu = cdot<R>(k, su);
+    const R e = R(kW3[k]) * (R(4.5) * cdu * csu - R(1.5) * dusu), dd = R(3 * kW3[k]) * cdu;
+    hout[k] = g[k] * ((sg[k] + K) - cB) + C.rho0 * (e + dd);
+    hout[k + 1] = g[k + 1] * ((sg[k + 1] + K) + cB) + C.rho0 * (e - dd);
   }
   return err;
 }
