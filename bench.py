@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"f32": 72, "f64": 144}
 # D3Q19 FP32 f-norm step: VALU wavefront instructions per wavefront (= per
 # site), profiles/step3_fp32_256cube_d3q19.md
-D3Q19_VALU_PER_SITE = 2839
+D3Q19_VALU_PER_SITE = 2482
 # sources of the step kernel (the one whose HBM traffic the profiles record)
 KERNEL_SOURCES = ["paper_1204_6734_amd/csrc/flb_device.hpp",
                   "paper_1204_6734_amd/csrc/flb_buffer.hpp",
