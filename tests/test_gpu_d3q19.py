@@ -70,6 +70,23 @@ def test_fp64_noise_matches_oracle(flb, basis):
         assert err <= 1e-12, (basis, k, err)
 
 
+@pytest.mark.parametrize("shape", [(3, 3, 3), (3, 5, 4), (65, 3, 3)])
+def test_degenerate_shapes_match_oracle(flb, shape):
+    """The smallest lattice and thin ones (rows that wrap inside one
+    wavefront, a ragged second tile), FP64 f-norm with noise, both phases."""
+    nx, ny, nz = shape
+    kw = dict(ux0=0.1, uy0=-0.05, uz0=0.03, kT=1e-4, tau=TAUS, seed=13)
+    g, o = both(flb, nx, ny, nz, flb.FP64, flb.BASIS_FNORM_LOCAL, **kw)
+    f = perturbed(nx, ny, nz, (0.1, -0.05, 0.03), seed=4)
+    g.set_populations(f)
+    o.set_populations(f)
+    for n in (1, 1, 5):
+        g.step(n)
+        o.step(n)
+        fg, fo = g.populations(), o.populations()
+        assert np.abs(fg - fo).max() <= 1e-12 * np.abs(fo).max(), (shape, o.t)
+
+
 def test_fp32_shifted_matches_fp64_oracle(flb):
     nx, ny, nz = 40, 8, 6
     kw = dict(ux0=0.1, uy0=0.05, uz0=0.0, kT=1e-4, tau=TAUS, seed=3)

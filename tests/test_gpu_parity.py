@@ -68,6 +68,29 @@ def test_fp64_noise_matches_oracle(flb, basis):
         assert err <= 1e-12, (basis, k, err)
 
 
+@pytest.mark.parametrize("nx,ny", [(3, 3), (3, 17), (65, 3), (64, 4), (4, 65)])
+def test_degenerate_shapes_match_oracle(flb, nx, ny):
+    """The smallest lattices and thin ones: a single partly filled tile whose
+    wavefronts wrap at both ends of a row, a tile row one site high, one
+    exact tile, a column of ragged tiles; FP64 f-norm trajectories with noise
+    at both streaming phases to 1e-12, and zero steps leave the state and
+    the clock alone."""
+    kw = dict(rho0=1.0, ux0=0.1, uy0=-0.05, kT=1e-4, tau=TAUS, seed=31, init=2)
+    g, o = both(flb, nx, ny, flb.FP64, 0, **kw)
+    fields = I.random_fields(nx, ny, seed=9, ux0=0.1, uy0=-0.05)
+    g.set_fields(*fields)
+    o.set_fields(*fields)
+    f0 = g.populations()
+    g.step(0)
+    assert g.t == 0
+    np.testing.assert_array_equal(g.populations(), f0)
+    for n in (1, 1, 7):
+        g.step(n)
+        o.step(n)
+        err = rel(g.populations(), o.populations())
+        assert err <= 1e-12, (nx, ny, o.t, err)
+
+
 def test_fp64_moments_match_oracle(flb):
     kw = dict(ux0=0.15, kT=1e-4, tau=TAUS, seed=3)
     g, o = both(flb, 45, 21, flb.FP64, **kw)
