@@ -68,16 +68,16 @@ def traffic_from_profiles(name: str):
 BASES = {"fnorm": ("fnorm_local", 0), "hermite": ("hermite", 1), "lut": ("fnorm_lut", 2)}
 
 
-def cpu_baseline(seconds: float = 12.0, basis: int = 0) -> dict:
+def cpu_baseline(seconds: float = 12.0, basis: int = 0, ux0: float = 0.1) -> dict:
     """FP64 oracle on a bounded sample: a 128 x 128 lattice with the large
     workload's parameters (and basis), stepped until ~`seconds` of CPU time."""
     import oracle as O
     from paper_1204_6734_amd import inputs as I
     nx = ny = 128
-    p = O.make_params(nx, ny, rho0=1.0, ux0=0.1, kT=1e-4, seed=1, init=O.INIT_FIELDS,
+    p = O.make_params(nx, ny, rho0=1.0, ux0=ux0, kT=1e-4, seed=1, init=O.INIT_FIELDS,
                       basis=basis)
     L = O.Lattice(p)
-    L.set_fields(*I.shear_wave_fields(nx, ny, ux0=0.1, amp=1e-3))
+    L.set_fields(*I.shear_wave_fields(nx, ny, ux0=ux0, amp=1e-3))
     L.step(5)
     steps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < seconds:
@@ -90,15 +90,15 @@ def cpu_baseline(seconds: float = 12.0, basis: int = 0) -> dict:
 
 
 def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 100,
-              launch=None, basis: str = "fnorm", precision: str = "fp32"):
+              launch=None, basis: str = "fnorm", precision: str = "fp32", ux0: float = 0.1):
     from paper_1204_6734_amd import inputs as I
     stream = torch.cuda.current_stream()
     bname, bcode = BASES[basis]
     fp32 = precision == "fp32"
     p = F.make_params(nx, nx, precision=F.FP32_SHIFTED if fp32 else F.FP64, basis=bcode,
-                      rho0=1.0, ux0=0.1, kT=1e-4, seed=1, init=F.INIT_FIELDS, sk_every=every)
+                      rho0=1.0, ux0=ux0, kT=1e-4, seed=1, init=F.INIT_FIELDS, sk_every=every)
     L = F.Lattice(p, stream=stream)
-    L.set_fields(*I.shear_wave_fields(nx, nx, ux0=0.1, amp=1e-3))
+    L.set_fields(*I.shear_wave_fields(nx, nx, ux0=ux0, amp=1e-3))
     if launch is None:
         tune = L.autotune(reps=3)  # trial steps run on a copy of the state
     else:
@@ -135,15 +135,19 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
             "launch": {"chosen": L.get_launch(), "candidates": tune},
             "config": {"workload": f"{nx}x{nx} D2Q9 {'FP32-shifted' if fp32 else 'FP64'}, "
                                    f"{'' if basis == 'fnorm' else bname + ' basis, '}"
-                                   f"rho0=1, u_x0=0.1, kT=1e-4, "
+                                   f"rho0=1, u_x0={ux0:g}, kT=1e-4, "
                                    f"tau=1, shear wave 1e-3 sin(2 pi x/L); " +
                                    (f"S(k) and j~_y(2 pi/L) every {every} steps" if every > 0
                                     else "no S(k), no mode log"),
                        "nx": nx, "ny": nx, "precision": "fp32_shifted" if fp32 else "fp64",
                        "basis": bname, "sk_every": every, "parallelism": "single GPU"},
             "dtype": "f32" if fp32 else "f64",
-            "kernel_label": f"step_kernel<{'float,float' if fp32 else 'double,double'},{bname}>",
-            "kernel_name": f"step_{precision}_{nx}" + ("" if basis == "fnorm" else f"_{basis}")}
+            # FP32 storage computes the collision in FP64 above |u0| = 0.25
+            "kernel_label": "step_kernel<%s,%s>" % (
+                ("float,float" if abs(ux0) <= 0.25 else "float,double") if fp32
+                else "double,double", bname),
+            "kernel_name": f"step_{precision}_{nx}" + ("" if basis == "fnorm" else f"_{basis}") +
+                           ("_fp64compute" if fp32 and abs(ux0) > 0.25 else "")}
 
 
 def run_ensemble(F, torch, steps: int, warmup: int, n: int = 64, side: int = 128,
@@ -304,6 +308,9 @@ def main():
                     help="collision basis of the large workload (default: the local f-norm)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
                     help="storage precision of the large workload (default: FP32-shifted)")
+    ap.add_argument("--ux0", type=float, default=0.1,
+                    help="background velocity of the large workload (above 0.25 the FP32-storage "
+                         "collision runs in FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -345,7 +352,7 @@ def main():
         return
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     r = run_large(F, torch, args.steps, args.warmup, nx=args.nx, every=args.sk_every,
-                  launch=launch, basis=args.basis, precision=args.precision)
+                  launch=launch, basis=args.basis, precision=args.precision, ux0=args.ux0)
     mlups = r["sites"] * args.steps / r["dt"] / 1e6
     bps = BYTES_PER_SITE[r["dtype"]]
     achieved = bps * r["sites"] / (r["kernel_ms"] * 1e-3) / 1e9
@@ -374,7 +381,7 @@ def main():
     if not args.no_serving:
         out["serving"] = run_serving(F, torch, nreq=args.requests or 40)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, BASES[args.basis][1])
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, BASES[args.basis][1], args.ux0)
     print(json.dumps(out), flush=True)
 
 
