@@ -479,8 +479,11 @@ __device__ __forceinline__ bool local_state(const R h[9], R rho0, R ux0, R uy0,
 }
 
 // One collision, eq. (6), on shifted populations h (in place).  Returns
-// error bits; on error h is left unchanged.
-template <typename R, int BASIS>
+// error bits; on error h is left unchanged.  NOISE32: draw the Gaussians in
+// FP32 although the collision runs in FP64 (FP32 storage above the FP32
+// basis speed: the stored result is rounded to FP32 anyway, and the FP32
+// transform is a sixth of the FP64 one's cost).
+template <typename R, int BASIS, bool NOISE32 = false>
 __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_t site,
                                        uint64_t t) {
   LocalState<R> S;
@@ -490,7 +493,16 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_
 
   // sqrt(rho) N: the local-density factor of the amplitudes of eq. (20)
   R N[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-  if (C.noise) site_gaussians<R>(C.k0, C.k1, site, t, 0u, S.rho, N);
+  if (C.noise) {
+    if constexpr (NOISE32) {
+      float n32[6];
+      site_gaussians<float>(C.k0, C.k1, site, t, 0u, (float)S.rho, n32);
+#pragma unroll
+      for (int a = 0; a < 6; ++a) N[a] = R(n32[a]);
+    } else {
+      site_gaussians<R>(C.k0, C.k1, site, t, 0u, S.rho, N);
+    }
+  }
 
   if (BASIS == kBasisHermite) {
     // App. A: n = w m, relaxation of M - M^0 with the same amplitudes.

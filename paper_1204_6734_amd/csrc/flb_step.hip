@@ -257,7 +257,7 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   if (!active) return;
   const CollideConst<R> C = collide_const<R>(sd);
   const uint32_t site = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
-  const int e = collide<R, BASIS>(h, C, site, t);
+  const int e = collide<R, BASIS, sizeof(S) < sizeof(R)>(h, C, site, t);
   if (e) {
     atomicOr(sd.err, e);
     atomicMin(sd.err_step, (unsigned long long)t);
