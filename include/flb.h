@@ -74,7 +74,9 @@ typedef struct {
   double tau[6];        /* relaxation times of modes 3..8 (Pi_xx-yy, Pi_xy,
                            Pi_xx+yy, q_x, q_y, eps), each > 1/2                   */
   uint64_t seed;        /* Philox key: noise is keyed by (seed, step, site)       */
-  int32_t precision;    /* flb_precision                                          */
+  int32_t precision;    /* flb_precision.  FP32_SHIFTED stores f - f^0(rho0, u0) in
+                           FP32 and collides in FP32 up to |u0| = 0.25, above it in
+                           FP64 (with FP32 Gaussians); FP64 does everything in FP64 */
   int32_t basis;        /* flb_basis                                              */
   int32_t init;         /* flb_init: EQUILIBRIUM f^0(rho0,u0); THERMAL adds ideal-
                            gas fluctuations sqrt(mu f^0) N; FIELDS waits for
