@@ -1,0 +1,41 @@
+"""Host logic of bench.py (no GPU): the one-GPU guard, the traffic lookup
+that only trusts counters taken on the current kernel sources, and the
+oracle baseline's record."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.join(os.path.dirname(__file__), "..")
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_traffic_is_used_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    with open(os.path.join(ROOT, "profiles", "step_fp32_8192_traffic.json")) as fh:
+        prof = json.load(fh)
+    assert bench.traffic_from_profiles("step_fp32_8192") == (
+        prof["bytes_per_launch"] if prof["kernel_hash"] == bench.kernel_hash() else None)
+    # a profile of other sources, or of another workload, is not used
+    (tmp_path / "profiles").mkdir()
+    stale = dict(prof, kernel_hash="0" * 16)
+    (tmp_path / "profiles" / "step_fp32_8192_traffic.json").write_text(json.dumps(stale))
+    current = bench.kernel_hash()
+    monkeypatch.setattr(bench, "kernel_hash", lambda: current)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_from_profiles("step_fp32_8192") is None
+    assert bench.traffic_from_profiles("step_fp64_8192") is None
+
+
+def test_cpu_baseline_record():
+    r = bench.cpu_baseline(seconds=0.5)
+    assert r["kind"] == "oracle" and r["unit"] == "MLUPS" and r["cores"] == 1
+    assert r["value"] > 0 and "128x128" in r["sample"]
