@@ -393,27 +393,6 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
 }
 
 // --------------------------------------------------------------- kernels
-__device__ __forceinline__ double select_bits(uint64_t mask, double a, double b) {
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  return __builtin_bit_cast(double, (ua & mask) | (ub & ~mask));
-}
-
-// Sum over the wavefront of 32 per-lane values; lanes 2v and 2v+1 end with
-// the total of value v (five butterfly passes halve the values per lane).
-__device__ __forceinline__ double wave_sum32(double (&v)[32], int lane) {
-#pragma unroll
-  for (int off = 32, n = 16; off >= 2; off >>= 1, n >>= 1) {
-    const uint64_t up = (lane & off) ? ~0ull : 0ull;
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-      const double send = select_bits(up, v[k], v[k + n]);
-      const double keep = select_bits(up, v[k + n], v[k]);
-      v[k] = keep + __shfl_xor(send, off, 64);
-    }
-  }
-  return v[0] + __shfl_xor(v[0], 1, 64);
-}
-
 // Statistic q of the correlator sums: df_i (q < 19) or df_i df_j (i <= j,
 // row-major) as index pairs, j = -1 for the first moments.
 struct StatIndex {
@@ -458,7 +437,7 @@ __device__ __forceinline__ void sample3(const R h[19], bool active, double* part
       else
         v[k] = df[kStat.i[q]] * df[kStat.j[q]];
     }
-    const double tot = wave_sum32(v, lane);
+    const double tot = wave_transpose_sum32(v, lane);
     if ((lane & 1) == 0) red[wave][group * 32 + (lane >> 1)] = tot;
   }
   __syncthreads();

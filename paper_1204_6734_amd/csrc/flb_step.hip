@@ -78,31 +78,6 @@ __device__ __forceinline__ CollideConst<double> collide_const<double>(const Slot
   return C;
 }
 
-// Sums of 32 per-lane values over a 64-lane wavefront, transposed: five
-// butterfly passes each halve the number of values a lane carries and a
-// last pass adds the two lanes that share a value, after which lanes 2v and
-// 2v+1 both hold the wave total of value v.
-__device__ __forceinline__ double pick(uint64_t mask, double a, double b) {
-  // a where mask is all ones, b where it is zero (bitwise, so the choice is
-  // never turned into a dynamically indexed array access)
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  return __builtin_bit_cast(double, (ua & mask) | (ub & ~mask));
-}
-
-__device__ __forceinline__ double wave_transpose_sum32(double (&v)[32], int lane) {
-#pragma unroll
-  for (int off = 32, n = 16; off >= 2; off >>= 1, n >>= 1) {
-    const uint64_t up = (lane & off) ? ~0ull : 0ull;
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-      const double send = pick(up, v[k], v[k + n]);
-      const double keep = pick(up, v[k + n], v[k]);
-      v[k] = keep + __shfl_xor(send, off, 64);
-    }
-  }
-  return v[0] + __shfl_xor(v[0], 1, 64);
-}
-
 // Correlator sums of df_i = f_i - f_i^0(rho0, u0) (= the stored h_i): 9
 // first moments and the 45 products i <= j (row-major), added to this
 // tile's open time-block partials.  Reduced in two groups of 32 values to
