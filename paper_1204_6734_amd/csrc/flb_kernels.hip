@@ -313,6 +313,19 @@ __device__ __forceinline__ void pass_load(V (&a)[E], const V* __restrict__ src, 
     for (int r = 0; r < R; ++r) a[m * R + r] = src[t + m * tpr + r * (n / R)];
 }
 
+// Twiddle w^k = exp(-2 pi i k / n), k < n, n a power of two.  FP64 reads the
+// table; FP32 evaluates it with the hardware sine and cosine, which take the
+// angle in revolutions (k / n is exact), to ~1e-7, the level of the FP32
+// transform itself: the table's gathers from L2 stalled every pass (a row
+// pass ran at half the speed it reaches without them).
+__device__ __forceinline__ double2 twiddle(const double2* __restrict__ tw, int k, int) {
+  return tw[k];
+}
+__device__ __forceinline__ float2 twiddle(const float2* __restrict__, int k, int n) {
+  const float a = (float)k * (1.0f / (float)n);
+  return float2{__builtin_amdgcn_cosf(a), -__builtin_amdgcn_sinf(a)};
+}
+
 template <int R, int E, typename V>
 __device__ __forceinline__ void pass_compute(V (&a)[E], int n, int t, int Ns,
                                              const V* __restrict__ tw) {
@@ -323,7 +336,7 @@ __device__ __forceinline__ void pass_compute(V (&a)[E], int n, int t, int Ns,
       const int j = t + m * tpr;
       const int step = (j & (Ns - 1)) * (n / (Ns * R));
 #pragma unroll
-      for (int r = 1; r < R; ++r) a[m * R + r] = cmul(a[m * R + r], tw[r * step]);
+      for (int r = 1; r < R; ++r) a[m * R + r] = cmul(a[m * R + r], twiddle(tw, r * step, n));
     }
     dft<R>(&a[m * R]);
   }
