@@ -128,18 +128,16 @@ def test_16384_row_fp32_structure_factor_matches_oracle(flb):
         assert np.abs(g.structure_factor(w) - o.structure_factor(w)).max() <= 2e-5 * scale, w
 
 
-def test_16384_fp32_sampled_sites_by_rows(flb):
-    """The largest lattice of the tests: 16384^2 FP32-shifted (9.7 GB of
-    populations, 1 GiB planes, 4x the benchmark), thermal start.  Sampled
-    sites (corners, edges, random) after an odd and an even step against the
-    oracle's collision of their neighbours, reading only the rows needed."""
-    nx = ny = 16384
+def sampled_sites_by_rows(F, nx, ny, precision, tol, what):
+    """Sampled sites (corners, edges, random) after an odd and an even step
+    against the oracle's collision of their neighbours, reading only the
+    rows needed; thermal start."""
     kw = dict(ux0=0.1, kT=1e-4, seed=3, tau=I.mixed_taus(2))
-    L = flb.Lattice(flb.make_params(nx, ny, precision=flb.FP32_SHIFTED, init=flb.INIT_THERMAL,
-                                    **kw))
+    L = F.Lattice(F.make_params(nx, ny, precision=precision, init=F.INIT_THERMAL, **kw))
     po = O.make_params(nx, ny, **kw)
     rng = np.random.default_rng(4)
-    sites = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1), (8191, 8192), (64, ny - 1)]
+    sites = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1), (nx // 2 - 1, ny // 2),
+             (64, ny - 1)]
     sites += [(int(a), int(b)) for a, b in zip(rng.integers(0, nx, 20), rng.integers(0, ny, 20))]
     L.step(3)
     for _ in range(2):  # odd phase, then even phase
@@ -156,5 +154,20 @@ def test_16384_fp32_sampled_sites_by_rows(flb):
                 fo = O.collide(po, before[ys][:, xs], site=ys * nx + xs, step=t)
                 want[i] = fo[i]
             err = max(err, np.abs(got - want).max())
-        print(f"16384^2 step {t}: max |f - oracle| = {err:.2e}")
-        assert err <= 2e-7, (t, err)
+        print(f"{what} step {t}: max |f - oracle| = {err:.2e}")
+        assert err <= tol, (what, t, err)
+
+
+def test_16384_fp32_sampled_sites_by_rows(flb):
+    """16384^2 FP32-shifted: 9.7 GB of populations, 1 GiB planes, 4x the
+    benchmark."""
+    sampled_sites_by_rows(flb, 16384, 16384, flb.FP32_SHIFTED, 2e-7, "16384^2 FP32")
+
+
+def test_largest_fp64_lattice_sampled_sites_by_rows(flb):
+    """The largest square lattice the library accepts (9 nx ny < 2^32):
+    21845^2 FP64, 34 GB of populations in 3.8 GB planes, where the 32-bit
+    byte offsets of the buffer accesses reach 89 % of their range."""
+    n = 21845
+    assert 9 * n * n < 2 ** 32 and 9 * (n + 1) * (n + 1) >= 2 ** 32
+    sampled_sites_by_rows(flb, n, n, flb.FP64, 1e-14, "21845^2 FP64")
