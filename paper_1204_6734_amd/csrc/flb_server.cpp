@@ -145,6 +145,7 @@ struct flb_server {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
   int admit_locked();
+  int finish(const Active& a);
   int retire();
   int run_chunk();
   int pump(int max_chunks, int* did);
@@ -191,15 +192,19 @@ int flb_server::admit_locked() {
     a.stats.reset(a.p.block_steps);
     // state: equilibrium (or thermal) start, cleared sums and flags
     const double mu = a.p.init == FLB_INIT_THERMAL ? 3.0 * a.p.kT : 0.0;
-    HIPC(launch_init(cfg.precision == 0 ? 0 : 1, a.desc.pop, nullptr, nullptr, nullptr, a.p.rho0,
-                     a.p.ux0, a.p.uy0, slot_shift(a.desc), a.p.nx, a.p.ny, mu, a.desc.k0,
-                     a.desc.k1, 0, 0, a.p.ny, st));
-    if (a.desc.partials) {
-      HIPC(launch_fill(a.desc.partials, (size_t)a.desc.ntiles * kNStat, 0.0, st));
-      HIPC(launch_fill(records, (size_t)kServerBlocks * kNStat, 0.0, st));
+    hipError_t e = launch_init(cfg.precision == 0 ? 0 : 1, a.desc.pop, nullptr, nullptr, nullptr,
+                               a.p.rho0, a.p.ux0, a.p.uy0, slot_shift(a.desc), a.p.nx, a.p.ny,
+                               mu, a.desc.k0, a.desc.k1, 0, 0, a.p.ny, st);
+    if (e == hipSuccess && a.desc.partials) {
+      e = launch_fill(a.desc.partials, (size_t)a.desc.ntiles * kNStat, 0.0, st);
+      if (e == hipSuccess) e = launch_fill(records, (size_t)kServerBlocks * kNStat, 0.0, st);
     }
-    HIPC(hipMemsetAsync(a.desc.err, 0, 4, st));
-    HIPC(hipMemsetAsync(a.desc.err_step, 0xFF, 8, st));
+    if (e == hipSuccess) e = hipMemsetAsync(a.desc.err, 0, 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(a.desc.err_step, 0xFF, 8, st);
+    if (e != hipSuccess) {
+      fl.release(off, bytes);  // the request stays queued
+      return hip_fail(e, "request set-up");
+    }
     active.push_back(a);
     queue.pop_front();
   }
@@ -214,51 +219,61 @@ static double* records_of(const Active& a, char* arena, int precision) {
   return (double*)(arena + a.off + o);
 }
 
-// Requests whose own time reached nsteps: read their correlators, free them.
+// Reads the correlators of a request that reached its step count, queues its
+// result and returns its memory.  On a HIP error nothing is released.
+int flb_server::finish(const Active& a) {
+  flb_result res;
+  std::memset(&res, 0, sizeof(res));
+  res.id = a.id;
+  res.tag = a.tag;
+  res.nsteps = a.nsteps;
+  res.t_submit = a.t_submit;
+  res.t_admit = a.t_admit;
+  int err = 0;
+  HIPC(hipMemcpy(&err, a.desc.err, 4, hipMemcpyDeviceToHost));
+  res.status = err ? ((err & kErrInvalidVelocity) ? FLB_E_INVALID_VELOCITY : FLB_E_NONFINITE)
+                   : FLB_OK;
+  if (a.desc.partials && !err) {
+    double* rec = records_of(a, arena, cfg.precision);
+    HIPC(launch_open_sum(a.desc.partials, a.desc.ntiles, d_open, st));
+    double open[kNStat];
+    std::vector<double> recs((size_t)std::max<uint64_t>(a.stats.nb, 1) * kNStat);
+    HIPC(hipMemcpyAsync(open, d_open, sizeof(open), hipMemcpyDeviceToHost, st));
+    if (a.stats.nb)
+      HIPC(hipMemcpyAsync(recs.data(), rec, a.stats.nb * kNStat * 8, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    double mt0[81];
+    fnorm_rows(a.p.ux0, a.p.uy0, mt0);
+    finish_covariance(a.stats, recs, open, (uint64_t)a.p.nx * a.p.ny, mt0, &res.cov);
+  }
+  res.t_done = now();
+  fl.release(a.off, a.bytes);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    results.push_back(res);
+    completed += 1;
+  }
+  done_cv.notify_all();
+  return FLB_OK;
+}
+
+// Retires every request whose own time reached nsteps.  The list of active
+// requests is replaced under the lock (other threads read its size); after a
+// failure the requests not yet retired stay in it.
 int flb_server::retire() {
   HIPC(hipStreamSynchronize(st));
   std::vector<Active> keep;
-  for (auto& a : active) {
-    const uint64_t own = a.desc.t0 + clock;
-    if (own < a.nsteps) {
-      keep.push_back(a);
-      continue;
+  int rc = FLB_OK;
+  for (const Active& a : active) {
+    if (rc == FLB_OK && a.desc.t0 + clock >= a.nsteps) {
+      rc = finish(a);
+      if (rc == FLB_OK) continue;
     }
-    flb_result res;
-    std::memset(&res, 0, sizeof(res));
-    res.id = a.id;
-    res.tag = a.tag;
-    res.nsteps = a.nsteps;
-    res.t_submit = a.t_submit;
-    res.t_admit = a.t_admit;
-    int err = 0;
-    HIPC(hipMemcpy(&err, a.desc.err, 4, hipMemcpyDeviceToHost));
-    res.status = err ? ((err & kErrInvalidVelocity) ? FLB_E_INVALID_VELOCITY : FLB_E_NONFINITE)
-                     : FLB_OK;
-    if (a.desc.partials && !err) {
-      double* rec = records_of(a, arena, cfg.precision);
-      HIPC(launch_open_sum(a.desc.partials, a.desc.ntiles, d_open, st));
-      double open[kNStat];
-      std::vector<double> recs((size_t)std::max<uint64_t>(a.stats.nb, 1) * kNStat);
-      HIPC(hipMemcpyAsync(open, d_open, sizeof(open), hipMemcpyDeviceToHost, st));
-      if (a.stats.nb)
-        HIPC(hipMemcpyAsync(recs.data(), rec, a.stats.nb * kNStat * 8, hipMemcpyDeviceToHost, st));
-      HIPC(hipStreamSynchronize(st));
-      double mt0[81];
-      fnorm_rows(a.p.ux0, a.p.uy0, mt0);
-      finish_covariance(a.stats, recs, open, (uint64_t)a.p.nx * a.p.ny, mt0, &res.cov);
-    }
-    res.t_done = now();
-    fl.release(a.off, a.bytes);
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      results.push_back(res);
-      completed += 1;
-    }
-    done_cv.notify_all();
+    keep.push_back(a);
   }
+  std::lock_guard<std::mutex> lk(mu);
   active.swap(keep);
-  return FLB_OK;
+  return rc;
 }
 
 // One chunk: upload the slot tables, launch chunk_steps batched steps, tick.
@@ -326,6 +341,7 @@ int flb_server::pump(int max_chunks, int* did) {
     if (rc != FLB_OK) return rc;
     rc = retire();
     if (rc != FLB_OK) return rc;
+    std::lock_guard<std::mutex> lk(mu);
     busy += now() - t0;
   }
   if (did) *did = n;
