@@ -208,6 +208,15 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def _host_f64(x, size: int, what: str) -> np.ndarray:
+    """Contiguous FP64 copy (or view) of x, which must hold `size` values: the
+    library reads exactly that many from the pointer it is given."""
+    a = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    if a.size != size:
+        raise ValueError(f"{what}: expected {size} values, got {a.size}")
+    return a
+
+
 def make_params(nx, ny, rho0=1.0, ux0=0.0, uy0=0.0, kT=0.0, tau=(1.0,) * 6, seed=1,
                 precision=FP32_SHIFTED, basis=BASIS_FNORM_LOCAL, init=INIT_EQUILIBRIUM,
                 sample_every=0, sk_every=0, block_steps=0) -> Params:
@@ -300,11 +309,11 @@ class Lattice(_Tunable):
             pass
 
     def set_fields(self, rho, ux, uy):
-        r, a, b = (np.ascontiguousarray(x, dtype=np.float64).reshape(-1) for x in (rho, ux, uy))
+        r, a, b = (_host_f64(x, self.n, "set_fields") for x in (rho, ux, uy))
         _check(load().flb_lattice_set_fields(self.h, _dp(r), _dp(a), _dp(b)), "set_fields")
 
     def set_populations(self, f, t: int = 0):
-        f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, -1)
+        f = _host_f64(f, 9 * self.n, "set_populations")
         _check(load().flb_lattice_set_populations(self.h, _dp(f), t), "set_populations")
 
     def step(self, n: int):
@@ -478,7 +487,7 @@ class Lattice3:
             pass
 
     def set_populations(self, f, t: int = 0):
-        fa = np.ascontiguousarray(f, dtype=np.float64)
+        fa = _host_f64(f, 19 * self.p.nx * self.p.ny * self.p.nz, "set_populations3")
         _check(load().flb3_lattice_set_populations(self.h, _dp(fa), t), "set_populations3")
 
     def step(self, n: int):
@@ -566,15 +575,23 @@ class Server:
         return did.value
 
     def poll(self, max_results: int = 1024) -> list:
+        """Completed results, oldest first.  If the server has stopped on an
+        error, raises FlbError with the results delivered by this call in its
+        `results` attribute."""
         buf = (Result * max_results)()
         n = C.c_int32()
-        _check(load().flb_server_poll(self.h, buf, max_results, C.byref(n)), "poll")
+        rc = load().flb_server_poll(self.h, buf, max_results, C.byref(n))
         out = []
         for k in range(n.value):
             r = buf[k]
             out.append({"id": r.id, "tag": r.tag, "status": r.status, "nsteps": r.nsteps,
                         "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done,
                         "cov": _cov_dict(r.cov)})
+        try:
+            _check(rc, "poll")
+        except FlbError as e:
+            e.results = out
+            raise
         return out
 
     def drain(self):

@@ -105,3 +105,16 @@ def test_copy_probe_argument_errors():
     for args in [(0, 1024, 5), (33, 1024, 5), (9, 0, 5), (9, 1 << 32, 5), (9, 1024, 0)]:
         assert lib.flb_copy_probe(*args, C.byref(ms)) == F.E_ARG
     assert lib.flb_copy_probe(9, 1024, 5, None) == F.E_ARG
+
+
+def test_host_arrays_are_size_checked_before_the_call():
+    """The library reads exactly 9 nx ny (or nx ny) doubles from the pointer it
+    is given; the binding refuses arrays of another size."""
+    import numpy as np
+    import paper_1204_6734_amd as F
+    ok = F._host_f64(np.zeros((9, 4, 5), np.float32), 180, "t")
+    assert ok.dtype == np.float64 and ok.flags.c_contiguous and ok.size == 180
+    with pytest.raises(ValueError):
+        F._host_f64(np.zeros((9, 4, 4)), 180, "t")
+    with pytest.raises(ValueError):
+        F._host_f64(np.zeros(181), 180, "t")
