@@ -167,7 +167,10 @@ int flb_lattice_reset_stats(flb_lattice* L);
 
 /* Checkpoint: exact storage bits plus time and parameters; restoring into a
  * lattice with the same parameters continues bit-identically (the noise is
- * keyed by the step).  Statistics are not part of the checkpoint. */
+ * keyed by the step).  Statistics are not part of the checkpoint.  restore
+ * needs the same nx, ny, precision, rho0 and u0 (the stored values are
+ * offsets from f^0(rho0, u0)), else FLB_E_ARG; kT, tau, seed, basis and
+ * sampling may differ and take effect from the restored step on. */
 size_t flb_lattice_checkpoint_bytes(flb_lattice* L);
 int flb_lattice_checkpoint(flb_lattice* L, void* host, size_t bytes);
 int flb_lattice_restore(flb_lattice* L, const void* host, size_t bytes);

@@ -639,6 +639,9 @@ int Group::restore(const void* host, size_t bytes) {
   if (h.p.nx != p.nx || h.p.ny != p.ny || h.p.precision != p.precision ||
       h.payload + sizeof(h) != checkpoint_bytes() || bytes < checkpoint_bytes())
     return set_error(FLB_E_ARG, "checkpoint does not match this lattice");
+  // the stored values are offsets from f^0(rho0, u0): the reference state must agree
+  if (h.p.rho0 != p.rho0 || h.p.ux0 != p.ux0 || h.p.uy0 != p.uy0)
+    return set_error(FLB_E_ARG, "checkpoint taken with another rho0 or u0");
   t = h.t;
   HIPC(hipMemcpyAsync(d_clock, &t, sizeof(uint64_t), hipMemcpyHostToDevice, st));
   const char* src = (const char*)host + sizeof(h);

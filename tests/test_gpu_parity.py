@@ -205,6 +205,15 @@ def test_checkpoint_restore_is_bit_identical(flb):
         assert c.t == 20
         c.step(17)
         np.testing.assert_array_equal(a.populations(), c.populations())
+        # another reference state cannot take these offsets; another kT can
+        other = flb.make_params(50, 17, precision=prec, ux0=0.11, kT=1e-4, tau=TAUS, seed=4)
+        with pytest.raises(flb.FlbError) as e:
+            flb.Lattice(other).restore(blob)
+        assert e.value.code == flb.E_ARG
+        hot = flb.Lattice(flb.make_params(50, 17, precision=prec, ux0=0.1, kT=2e-4, tau=TAUS,
+                                          seed=4))
+        hot.restore(blob)
+        np.testing.assert_array_equal(hot.populations(), b.populations())
 
 
 def test_in_place_streaming_preserves_mass_and_momentum(flb):
