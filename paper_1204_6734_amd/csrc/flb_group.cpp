@@ -288,9 +288,6 @@ int Group::launch_one(uint32_t k, bool sample, int odd) {
   return FLB_OK;
 }
 
-// Whether every slot samples at every step or never (then the step schedule
-// inside a chunk does not depend on the time and a captured graph can be
-// replayed), and no structure factors are taken.
 // A captured chunk of graph_chunk steps can be replayed at every time that
 // is a multiple of graph_chunk when each slot's sampling interval divides the
 // chunk (the sampling pattern inside a chunk is then the same every time)
@@ -826,6 +823,8 @@ int flb_ensemble_create(const flb_params* ps, int32_t n, void* hip_stream, flb_e
 int flb_ensemble_set_graph_chunk(flb_ensemble* E, int32_t steps) {
   NEED(E);
   if (steps < 0 || steps > (1 << 16)) return flb::set_error(FLB_E_ARG, "bad chunk %d", steps);
+  const hipError_t e = hipStreamSynchronize(E->g.st);  // no replay in flight
+  if (e != hipSuccess) return flb::hip_fail(e, "sync");
   E->g.drop_graph();
   E->g.graph_chunk = steps + (steps & 1);  // even: replays keep the streaming phase
   return FLB_OK;

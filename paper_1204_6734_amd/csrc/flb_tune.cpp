@@ -156,33 +156,39 @@ int Group::autotune(int reps, flb_launch_config* results, int max_results, int* 
     meas.push_back(flb_launch_config{c.tiles_per_block, c.grid_blocks, 1e30});
   // warm the device up (clocks ramp over tens of milliseconds) for at least
   // 8 pairs or 50 ms, then time every candidate in two interleaved rounds and
-  // keep each one's faster round
-  {
-    HIPC(hipEventRecord(e0, st));
-    for (int w = 0; w < 1000; ++w) {
-      HIPC(pair(cand[0]));
-      if (w >= 7 && (w & 7) == 7) {
-        HIPC(hipEventRecord(e1, st));
-        HIPC(hipEventSynchronize(e1));
+  // keep each one's faster round.  The snapshot is put back whether or not
+  // the trials succeed.
+  auto trials = [&]() -> hipError_t {
+    hipError_t r = hipEventRecord(e0, st);
+    for (int w = 0; w < 1000 && r == hipSuccess; ++w) {
+      r = pair(cand[0]);
+      if (r == hipSuccess && w >= 7 && (w & 7) == 7) {
+        r = hipEventRecord(e1, st);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
         float ms = 0.f;
-        HIPC(hipEventElapsedTime(&ms, e0, e1));
-        if (ms > 50.f) break;
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        if (r == hipSuccess && ms > 50.f) break;
       }
     }
-  }
-  for (int round = 0; round < 2; ++round) {
-    for (size_t i = 0; i < cand.size(); ++i) {
-      HIPC(pair(cand[i]));  // first launches of a shape
-      HIPC(hipEventRecord(e0, st));
-      for (int r = 0; r < reps; ++r) HIPC(pair(cand[i]));
-      HIPC(hipEventRecord(e1, st));
-      HIPC(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPC(hipEventElapsedTime(&ms, e0, e1));
-      meas[i].ms_per_step = std::min(meas[i].ms_per_step, ms / (2.0 * reps));
+    for (int round = 0; round < 2 && r == hipSuccess; ++round) {
+      for (size_t i = 0; i < cand.size() && r == hipSuccess; ++i) {
+        r = pair(cand[i]);  // first launches of a shape
+        if (r == hipSuccess) r = hipEventRecord(e0, st);
+        for (int k = 0; k < reps && r == hipSuccess; ++k) r = pair(cand[i]);
+        if (r == hipSuccess) r = hipEventRecord(e1, st);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        if (r == hipSuccess)
+          meas[i].ms_per_step = std::min(meas[i].ms_per_step, ms / (2.0 * reps));
+      }
     }
-  }
-  HIPC(copy(false));
+    return r;
+  };
+  const hipError_t tr = trials();
+  const hipError_t back = copy(false);
+  if (tr != hipSuccess) return hip_fail(tr, "autotune trial steps");
+  if (back != hipSuccess) return hip_fail(back, "autotune: restoring the populations");
   HIPC(hipStreamSynchronize(st));
   std::stable_sort(meas.begin(), meas.end(),
                    [](const flb_launch_config& a, const flb_launch_config& b) {
