@@ -393,52 +393,61 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
 }
 
 // --------------------------------------------------------------- kernels
-// Statistic q of the correlator sums: df_i (q < 19) or df_i df_j (i <= j,
-// row-major) as index pairs, j = -1 for the first moments.
-struct StatIndex {
-  int i[kNStat3], j[kNStat3];
-};
-constexpr StatIndex stat_index() {
-  StatIndex s{};
-  int q = 0;
-  for (int i = 0; i < 19; ++i, ++q) {
-    s.i[q] = i;
-    s.j[q] = -1;
-  }
-  for (int i = 0; i < 19; ++i)
-    for (int j = i; j < 19; ++j, ++q) {
-      s.i[q] = i;
-      s.j[q] = j;
-    }
-  return s;
-}
-constexpr StatIndex kStat = stat_index();
+// Correlator statistics: q < 19 is the sum of df_q; the products df_i df_j,
+// i <= j, follow row by row.
+typedef double double4_v3 __attribute__((ext_vector_type(4)));
 
-// Correlator sums of df = h (the 209 statistics above), added to this
-// tile's partials; the whole workgroup calls this.  Seven groups of 32
-// values are reduced over the wavefront by transposing butterflies.
-template <typename R>
+// Index of the product statistic (i, j), i <= j, in the layout above.
+__device__ __forceinline__ int stat_pair(int i, int j) {
+  return 19 + 19 * i - (i * (i - 1)) / 2 + (j - i);
+}
+
+// Correlator sums of df = h (the 209 statistics), added to this
+// tile's partials; the whole workgroup calls this.  For one wavefront they
+// are the entries of X^T X, X the 64 x 20 matrix of the nineteen df_i and a
+// constant 1 per site, split into column blocks X0 (df_0..df_15) and X1
+// (df_16..df_18, the constant, zeros): X0^T X0, X0^T X1 and X1^T X1 take
+// sixteen FP64 matrix instructions each (16 x 16 output, four sites per
+// instruction), on values the wavefront stages in LDS; lane l reads column
+// l % 16 of site l / 16 of each group of four and holds output row
+// l / 16 + 4 r, column l % 16 in element r.  The four wavefronts then add
+// their sums in a fixed order.
+template <typename S, typename R>
 __device__ __forceinline__ void sample3(const R h[19], bool active, double* partials) {
+  __shared__ S xs[4][64 * 19];
   __shared__ double red[4][224];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double df[19];
+  S* x = xs[wave];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) df[i] = active ? (double)h[i] : 0.0;
+  for (int i = 0; i < 19; ++i) x[lane * 19 + i] = active ? (S)h[i] : S(0);
+  // the values come back from other lanes of the same wavefront, whose LDS
+  // accesses complete in program order
+  __builtin_amdgcn_wave_barrier();
+  const int col = lane & 15, grp = lane >> 4;
+  const int c1 = col < 3 ? 16 + col : 18;  // in-range column of block 1
+  const double pad1 = col == 3 ? 1.0 : 0.0;
+  double4_v3 a00 = {0.0, 0.0, 0.0, 0.0}, a01 = a00, a11 = a00;
 #pragma unroll
-  for (int group = 0; group < 7; ++group) {
-    double v[32];
+  for (int q = 0; q < 16; ++q) {
+    const S* row = x + (4 * q + grp) * 19;
+    const double v0 = (double)row[col];
+    const S r1 = row[c1];
+    const double v1 = col < 3 ? (double)r1 : pad1;
+    a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, v0, a00, 0, 0, 0);
+    a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, v1, a01, 0, 0, 0);
+    a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, v1, a11, 0, 0, 0);
+  }
+  double* rw = red[wave];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int q = group * 32 + k;
-      if (q >= kNStat3)
-        v[k] = 0.0;
-      else if (kStat.j[q] < 0)
-        v[k] = df[kStat.i[q]];
-      else
-        v[k] = df[kStat.i[q]] * df[kStat.j[q]];
-    }
-    const double tot = wave_transpose_sum32(v, lane);
-    if ((lane & 1) == 0) red[wave][group * 32 + (lane >> 1)] = tot;
+  for (int r = 0; r < 4; ++r) {
+    const int i = grp + 4 * r;  // output row, 0..15
+    if (i <= col) rw[stat_pair(i, col)] = a00[r];
+    if (col < 3) rw[stat_pair(i, 16 + col)] = a01[r];
+    if (col == 3) rw[i] = a01[r];  // sum of df_i
+  }
+  if (grp < 3) {  // rows 16..18 of block 1 (element 0 of lanes 0..47)
+    if (col < 3 && grp <= col) rw[stat_pair(16 + grp, 16 + col)] = a11[0];
+    if (col == 3) rw[16 + grp] = a11[0];
   }
   __syncthreads();
   if (threadIdx.x < kNStat3)
@@ -509,7 +518,7 @@ step3_kernel(const Desc3* __restrict__ desc, const uint64_t* __restrict__ clock,
   }
   if (SAMPLE) {
     if (d.sample_every > 0 && t % (uint64_t)d.sample_every == 0)
-      sample3<R>(h, active, d.partials + (size_t)tile * kNStat3);
+      sample3<S, R>(h, active, d.partials + (size_t)tile * kNStat3);
   }
   if (!active) return;
   const Const3<R> C = const3<R>(d);

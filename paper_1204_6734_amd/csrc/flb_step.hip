@@ -78,43 +78,59 @@ __device__ __forceinline__ CollideConst<double> collide_const<double>(const Slot
   return C;
 }
 
+// Workgroups of the sampling step variants hold at most two tiles.
+constexpr int kSampleTilesPerBlock = 2;
+
+typedef double double4_v __attribute__((ext_vector_type(4)));
+
 // Correlator sums of df_i = f_i - f_i^0(rho0, u0) (= the stored h_i): 9
 // first moments and the 45 products i <= j (row-major), added to this
-// tile's open time-block partials.  Reduced in two groups of 32 values to
-// keep registers low.  Every thread of the workgroup calls this (it holds
-// two workgroup barriers); `due` is uniform over one tile and says whether
-// the tile samples at all.  The partial of a tile is always formed in the
-// same order, whatever the workgroup shape.
-template <typename R>
+// tile's open time-block partials.  For one wavefront (64 sites) these are
+// the entries of X^T X, X the 64 x 10 matrix of the nine df_i and a
+// constant 1 per site: sixteen FP64 matrix instructions (16 x 16 output, four
+// sites per instruction) after the wavefront has staged its values in LDS,
+// where lane l picks column l % 16 of site l / 16 of each group of four.  The
+// instruction leaves output row l / 16 + 4 r, column l % 16 in element r of
+// lane l.  The four wavefronts of the tile then add their sums in a fixed
+// order, so a tile's partial does not depend on the workgroup shape.  Every
+// thread of the workgroup calls this (it holds two workgroup barriers);
+// `due` is uniform over one tile and says whether the tile samples at all.
+// Sites outside the lattice stage zeros.
+template <typename S, typename R>
 __device__ __forceinline__ void sample_correlators(const R h[9], bool active, bool due,
                                                    double* __restrict__ partials, int sub,
                                                    int wave) {
-  __shared__ double red[kMaxTilesPerBlock][kTileY][kTileX];
+  __shared__ S xs[kSampleTilesPerBlock][kTileY][kTileX * 9];
+  __shared__ double red[kSampleTilesPerBlock][kTileY][kTileX];
   const int lane = threadIdx.x & 63;
   if (due) {
-    double df[9];
+    S* x = xs[sub][wave];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) df[i] = active ? (double)h[i] : 0.0;
+    for (int i = 0; i < 9; ++i) x[lane * 9 + i] = active ? (S)h[i] : S(0);
+    // the values come back from other lanes of the same wavefront, whose LDS
+    // accesses complete in program order
+    __builtin_amdgcn_wave_barrier();
+    const int col = lane & 15, grp = lane >> 4;
+    // columns 10..15 are zero and column 9 is the constant; every lane reads
+    // an in-range element so that the sixteen reads issue back to back
+    const int colr = col < 9 ? col : 8;
+    const double pad = col == 9 ? 1.0 : 0.0;
+    S xv[16];
 #pragma unroll
-    for (int group = 0; group < 2; ++group) {
-      double v[32];
-      int k = 0, q = 0;
+    for (int q = 0; q < 16; ++q) xv[q] = x[(4 * q + grp) * 9 + colr];
+    double4_v acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        if (q >= group * 32 && q < group * 32 + 32) v[k++] = df[i];
-        ++q;
-      }
+    for (int q = 0; q < 16; ++q) {
+      const double v = col < 9 ? (double)xv[q] : pad;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    }
+    // row i = grp + 4 r, column col: sum_i = (i, 9), product (i, j <= 8) for i <= j
 #pragma unroll
-      for (int i = 0; i < 9; ++i)
-#pragma unroll
-        for (int j = i; j < 9; ++j) {
-          if (q >= group * 32 && q < group * 32 + 32) v[k++] = df[i] * df[j];
-          ++q;
-        }
-#pragma unroll
-      for (; k < 32; ++k) v[k] = 0.0;
-      const double tot = wave_transpose_sum32(v, lane);
-      if ((lane & 1) == 0) red[sub][wave][group * 32 + (lane >> 1)] = tot;
+    for (int r = 0; r < 4; ++r) {
+      const int i = grp + 4 * r;
+      if (i < 9 && col == 9) red[sub][wave][i] = acc[r];
+      if (i < 9 && col < 9 && i <= col)
+        red[sub][wave][9 + 9 * i - (i * (i - 1)) / 2 + (col - i)] = acc[r];
     }
   }
   __syncthreads();
@@ -123,7 +139,7 @@ __device__ __forceinline__ void sample_correlators(const R h[9], bool active, bo
     const double tot = (red[sub][0][v] + red[sub][1][v]) + (red[sub][2][v] + red[sub][3][v]);
     partials[v] += tot;
   }
-  __syncthreads();  // red is reused by the next tile group of a persistent grid
+  __syncthreads();  // red and xs are reused by the next tile
 }
 
 // Byte offsets (within their planes) of the nine populations a site reads
@@ -210,8 +226,8 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
 
   if (SAMPLE) {
     const bool due = live && sd.sample_every > 0 && t % (uint64_t)sd.sample_every == 0;
-    sample_correlators<R>(h, active, due, sd.partials + (size_t)(due ? lt : 0) * kNStat, sub,
-                          wave);
+    sample_correlators<S, R>(h, active, due, sd.partials + (size_t)(due ? lt : 0) * kNStat,
+                             sub, wave);
     if (live && sd.skz != nullptr && sd.sk_every > 0 && t % (uint64_t)sd.sk_every == 0 &&
         active) {
       // structure-factor fields in the f-norm at (rho0, u0): d rho and
@@ -249,6 +265,9 @@ template <typename R, bool SAMPLE>
 constexpr int max_tiles_per_block() {
   return (SAMPLE || sizeof(R) == 8) ? 2 : kMaxTilesPerBlock;
 }
+static_assert(max_tiles_per_block<float, true>() <= kSampleTilesPerBlock &&
+                  max_tiles_per_block<double, true>() <= kSampleTilesPerBlock,
+              "the correlator staging holds kSampleTilesPerBlock tiles");
 
 // The batched step: blockDim.x / 256 tiles per workgroup.  Without PERSIST
 // workgroup b takes tile group b; with PERSIST (a grid smaller than the
