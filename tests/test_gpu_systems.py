@@ -199,3 +199,19 @@ def test_ensemble_mixed_compute_classes_equal_alone(flb, chunk):
         L.step(25)
         np.testing.assert_array_equal(E.populations(i), L.populations())
         np.testing.assert_array_equal(E.covariance(i)["cov_f"], L.covariance()["cov_f"])
+
+
+def test_server_failing_request_leaves_the_others_unchanged(flb):
+    """A request whose thermal start at a high temperature leaves the validity
+    region reports FLB_E_INVALID_VELOCITY; the requests batched with it give
+    the same results as when they run alone."""
+    good = [(flb.make_params(48, 40, ux0=0.1, kT=1e-4, seed=400 + k, sample_every=1,
+                             block_steps=10), 60) for k in range(2)]
+    bad = (flb.make_params(40, 40, kT=0.05, seed=7, init=flb.INIT_THERMAL, sample_every=1), 60)
+    reqs = [good[0], bad, good[1]]
+    mix = _serve(flb, reqs, 64 << 20, slots=3, chunk=20)
+    assert mix[1]["status"] == flb.E_INVALID_VELOCITY
+    for k in (0, 2):
+        alone = _serve(flb, [reqs[k]], 64 << 20, slots=1, chunk=20)[0]
+        assert mix[k]["status"] == alone["status"] == 0
+        np.testing.assert_array_equal(mix[k]["cov"]["cov_f"], alone["cov"]["cov_f"])
