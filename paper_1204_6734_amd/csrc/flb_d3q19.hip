@@ -417,6 +417,9 @@ __device__ __forceinline__ void sample3(const R h[19], bool active, double* part
   __shared__ S xs[4][64 * 19];
   __shared__ double red[4][224];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the tile's open partial, read early so that its latency overlaps the sums
+  const bool adds = threadIdx.x < kNStat3;
+  const double open = adds ? partials[threadIdx.x] : 0.0;
   S* x = xs[wave];
 #pragma unroll
   for (int i = 0; i < 19; ++i) x[lane * 19 + i] = active ? (S)h[i] : S(0);
@@ -450,9 +453,9 @@ __device__ __forceinline__ void sample3(const R h[19], bool active, double* part
     if (col == 3) rw[16 + grp] = a11[0];
   }
   __syncthreads();
-  if (threadIdx.x < kNStat3)
-    partials[threadIdx.x] += (red[0][threadIdx.x] + red[1][threadIdx.x]) +
-                             (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  if (adds)
+    partials[threadIdx.x] = open + ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                    (red[2][threadIdx.x] + red[3][threadIdx.x]));
 }
 
 __device__ __forceinline__ uint32_t cell(int x, int y, int z, const Desc3& d) {
