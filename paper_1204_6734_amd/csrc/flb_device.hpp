@@ -483,9 +483,29 @@ __device__ __forceinline__ bool local_state(const R h[9], R rho0, R ux0, R uy0,
 // FP32 although the collision runs in FP64 (FP32 storage above the FP32
 // basis speed: the stored result is rounded to FP32 anyway, and the FP32
 // transform is a sixth of the FP64 one's cost).
+// Unit Gaussians of one (site, step), for a caller that draws them before
+// the populations of the site have arrived (the draw needs only the site
+// and the step); collide then scales them by sqrt(rho).
+template <typename R, bool NOISE32>
+__device__ __forceinline__ void unit_gaussians(const CollideConst<R>& C, uint32_t site,
+                                               uint64_t t, R N[6]) {
+  if constexpr (NOISE32) {
+    float n32[6];
+    site_gaussians<float>(C.k0, C.k1, site, t, 0u, 1.0f, n32);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) N[a] = R(n32[a]);
+  } else {
+    site_gaussians<R>(C.k0, C.k1, site, t, 0u, R(1), N);
+  }
+}
+
+// One collision (eq. (6)) of the shifted populations h in place.  Nu: the
+// site's unit Gaussians when the caller drew them (unit_gaussians), else
+// null and collide draws them itself with the density folded into the
+// Box-Muller radius.
 template <typename R, int BASIS, bool NOISE32 = false>
 __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_t site,
-                                       uint64_t t) {
+                                       uint64_t t, const R* Nu = nullptr) {
   LocalState<R> S;
   if (!local_state(h, C.rho0, C.ux0, C.uy0, S)) return kErrNonFinite;
   const R ux = S.ux, uy = S.uy;
@@ -493,7 +513,11 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_
 
   // sqrt(rho) N: the local-density factor of the amplitudes of eq. (20)
   R N[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-  if (C.noise) {
+  if (C.noise && Nu) {
+    const R sr = S.rho * rsqrt_t(S.rho);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) N[a] = Nu[a] * sr;
+  } else if (C.noise) {
     if constexpr (NOISE32) {
       float n32[6];
       site_gaussians<float>(C.k0, C.k1, site, t, 0u, (float)S.rho, n32);
