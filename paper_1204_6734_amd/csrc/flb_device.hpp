@@ -218,8 +218,8 @@ __device__ __forceinline__ void box_muller<double, 24>(uint32_t ua, uint32_t ub,
 // bits give six 21-bit integers (top 21 bits of each word, then the low 11
 // bits of words 0/2 joined with the low 10 bits of words 1/3) for
 // Box-Muller on the pairs (u0,u1), (u2,u3), (u4,u5).  v = 1 gives unit
-// Gaussians; the collision passes v = rho, the local-density factor of the
-// noise amplitude of eq. (20).
+// Gaussians (the collision's draw; it scales them by sqrt(rho), the
+// local-density factor of the noise amplitude of eq. (20)).
 template <typename R>
 __device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint32_t site,
                                                uint64_t step, uint32_t tag, R v, R N[6]) {
@@ -478,14 +478,12 @@ __device__ __forceinline__ bool local_state(const R h[9], R rho0, R ux0, R uy0,
   return true;
 }
 
-// One collision, eq. (6), on shifted populations h (in place).  Returns
-// error bits; on error h is left unchanged.  NOISE32: draw the Gaussians in
-// FP32 although the collision runs in FP64 (FP32 storage above the FP32
-// basis speed: the stored result is rounded to FP32 anyway, and the FP32
-// transform is a sixth of the FP64 one's cost).
-// Unit Gaussians of one (site, step), for a caller that draws them before
-// the populations of the site have arrived (the draw needs only the site
-// and the step); collide then scales them by sqrt(rho).
+// Unit Gaussians of one (site, step).  The draw needs only the site and the
+// step, so the step kernel makes it before the populations of the site have
+// arrived; collide scales them by sqrt(rho).  NOISE32: draw in FP32 although
+// the collision runs in FP64 (FP32 storage above the FP32 basis speed: the
+// stored result is rounded to FP32 anyway, and the FP32 transform is a sixth
+// of the FP64 one's cost).
 template <typename R, bool NOISE32>
 __device__ __forceinline__ void unit_gaussians(const CollideConst<R>& C, uint32_t site,
                                                uint64_t t, R N[6]) {
@@ -499,13 +497,11 @@ __device__ __forceinline__ void unit_gaussians(const CollideConst<R>& C, uint32_
   }
 }
 
-// One collision (eq. (6)) of the shifted populations h in place.  Nu: the
-// site's unit Gaussians when the caller drew them (unit_gaussians), else
-// null and collide draws them itself with the density folded into the
-// Box-Muller radius.
-template <typename R, int BASIS, bool NOISE32 = false>
-__device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_t site,
-                                       uint64_t t, const R* Nu = nullptr) {
+// One collision, eq. (6), on shifted populations h (in place), with the
+// site's unit Gaussians Nu (read only when the lattice has noise).  Returns
+// error bits; on error h is left unchanged.
+template <typename R, int BASIS>
+__device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, const R Nu[6]) {
   LocalState<R> S;
   if (!local_state(h, C.rho0, C.ux0, C.uy0, S)) return kErrNonFinite;
   const R ux = S.ux, uy = S.uy;
@@ -513,19 +509,10 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, uint32_
 
   // sqrt(rho) N: the local-density factor of the amplitudes of eq. (20)
   R N[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-  if (C.noise && Nu) {
+  if (C.noise) {
     const R sr = S.rho * rsqrt_t(S.rho);
 #pragma unroll
     for (int a = 0; a < 6; ++a) N[a] = Nu[a] * sr;
-  } else if (C.noise) {
-    if constexpr (NOISE32) {
-      float n32[6];
-      site_gaussians<float>(C.k0, C.k1, site, t, 0u, (float)S.rho, n32);
-#pragma unroll
-      for (int a = 0; a < 6; ++a) N[a] = R(n32[a]);
-    } else {
-      site_gaussians<R>(C.k0, C.k1, site, t, 0u, S.rho, N);
-    }
   }
 
   if (BASIS == kBasisHermite) {

@@ -248,13 +248,11 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   if (!active) return;
   const CollideConst<R> C = collide_const<R>(sd);
   const uint32_t site = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
-  // FP64 collisions run at three wavefronts per SIMD, too few to hide the
-  // load latency: their Gaussians (which need only the site and the step)
-  // are drawn here, while the loads are in flight
-  constexpr bool kEarlyNoise = sizeof(R) == 8;
+  // the Gaussians need only the site and the step: drawn here, while the
+  // loads are still in flight, they cover part of the load latency
   R Nu[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-  if (kEarlyNoise && C.noise) unit_gaussians<R, (sizeof(S) < sizeof(R))>(C, site, t, Nu);
-  const int e = collide<R, BASIS, sizeof(S) < sizeof(R)>(h, C, site, t, kEarlyNoise ? Nu : nullptr);
+  if (C.noise) unit_gaussians<R, (sizeof(S) < sizeof(R))>(C, site, t, Nu);
+  const int e = collide<R, BASIS>(h, C, Nu);
   if (e) {
     atomicOr(sd.err, e);
     atomicMin(sd.err_step, (unsigned long long)t);
