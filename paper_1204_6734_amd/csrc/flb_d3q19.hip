@@ -57,9 +57,10 @@ __device__ __forceinline__ Const3<double> const3<double>(const Desc3& d) {
   return c;
 }
 
-// Fifteen Gaussians of variance v (the local density) for one site and
-// step: four Philox4x32-10 blocks with counter (site, block, step lo, step
-// hi), key = seed; the top 24 bits of the sixteen words give uniforms
+// Fifteen Gaussians of variance v for one site and step (the step kernel
+// draws unit ones and scales them by the square root of the local density):
+// four Philox4x32-10 blocks with counter (site, block, step lo, step hi),
+// key = seed; the top 24 bits of the sixteen words give uniforms
 // (U + 1/2) 2^-24, and Box-Muller on consecutive pairs.
 template <typename R>
 __device__ __forceinline__ void gaussians15(uint32_t k0, uint32_t k1, uint32_t site, uint64_t t,
@@ -162,12 +163,21 @@ __device__ __forceinline__ void back3(const R y[15], R sg[19]) {
   }
 }
 
+// sqrt(rho) N from the site's unit Gaussians Nu (zeros without noise): the
+// local-density factor of the amplitudes of eq. (20).
+template <typename R>
+__device__ __forceinline__ void scaled_noise(int noise, R rho, const R Nu[15], R N[15]) {
+  const R sr = noise ? rho * rsqrt_t(rho) : R(0);
+#pragma unroll
+  for (int a = 0; a < 15; ++a) N[a] = Nu[a] * sr;
+}
+
 // The collision in the fixed Hermite-type rows with n = w m (BASIS 1), on
 // shifted populations h in place; returns error bits (h unchanged on error).
-template <typename R>
-__device__ __forceinline__ int collide3_hermite(R h[19], const Const3<R>& C, uint32_t k0,
-                                                uint32_t k1, int noise, uint32_t site,
-                                                uint64_t t) {
+template <typename R, bool DRAW>
+__device__ __forceinline__ int collide3_hermite(R h[19], const Const3<R>& C, int noise,
+                                                const R Nu[15], uint32_t k0, uint32_t k1,
+                                                uint32_t site, uint64_t t) {
   // moments of h in the basis rows (h = f - f^0(rho0, u0))
   R M[19];
   moments3(h, M);
@@ -205,9 +215,14 @@ __device__ __forceinline__ int collide3_hermite(R h[19], const Const3<R>& C, uin
     d[b - 4] = M[b] - (drho * pi + C.rho0 * dpi);
   }
   R N[15];
+  if constexpr (DRAW) {
+    // drawn here, with the local density folded into the Box-Muller radius
 #pragma unroll
-  for (int a = 0; a < 15; ++a) N[a] = R(0);
-  if (noise) gaussians15<R>(k0, k1, site, t, rho, N);
+    for (int a = 0; a < 15; ++a) N[a] = R(0);
+    if (noise) gaussians15<R>(k0, k1, site, t, rho, N);
+  } else {
+    scaled_noise(noise, rho, Nu, N);
+  }
 
   // Hermite-type rows with n = w m: relax d directly
   R Y[15];
@@ -241,9 +256,9 @@ constexpr int kPark = kParkRows * (kParkRows + 1) / 2;  // values per thread
 // caller reads the site's values again, so nothing of the input has to stay
 // live for the failing lanes while the others go on).
 template <typename R>
-__device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C, uint32_t k0,
-                                              uint32_t k1, int noise, uint32_t site, uint64_t t,
-                                              R* __restrict__ park, R hout[19]) {
+__device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C, int noise,
+                                              const R Nu[15], R* __restrict__ park,
+                                              R hout[19]) {
   R M[19];
   moments3(h, M);
   const R drho = M[0];
@@ -270,11 +285,9 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
   if (!(gmin > R(0))) return kErrInvalidVelocity;
   const int err = 0;
 
-  // the Gaussians first: they are consumed column by column below
+  // the scaled Gaussians first: they are consumed column by column below
   R N[15];
-#pragma unroll
-  for (int a = 0; a < 15; ++a) N[a] = R(0);
-  if (noise) gaussians15<R>(k0, k1, site, t, rho, N);
+  scaled_noise(noise, rho, Nu, N);
 
   const R mono[9] = {u[0], u[1], u[2], u[0] * u[0], u[1] * u[1], u[2] * u[2],
                      u[0] * u[1], u[0] * u[2], u[1] * u[2]};
@@ -519,20 +532,28 @@ step3_kernel(const Desc3* __restrict__ desc, const uint64_t* __restrict__ clock,
 #pragma unroll
     for (int i = 0; i < 19; ++i) h[i] = R(0);
   }
+  // the unit Gaussians need only the site and the step: drawn here, while
+  // the loads are still in flight, they cover part of the load latency
+  // (measured faster for every variant but the FP32 Hermite-row one, which
+  // is memory-bound and keeps drawing them inside its collision)
+  constexpr bool kEarlyNoise = !(sizeof(R) == 4 && BASIS == 1);
+  R Nu[15];
+#pragma unroll
+  for (int a = 0; a < 15; ++a) Nu[a] = R(0);
+  if (kEarlyNoise && d.noise && active) gaussians15<R>(d.k0, d.k1, cell(x, y, z, d), t, R(1), Nu);
   if (SAMPLE) {
     if (d.sample_every > 0 && t % (uint64_t)d.sample_every == 0)
       sample3<S, R>(h, active, d.partials + (size_t)tile * kNStat3);
   }
   if (!active) return;
   const Const3<R> C = const3<R>(d);
-  const uint32_t site = cell(x, y, z, d);
   __shared__ R park[BASIS == 0 ? kPark : 1][kBlock3];
   R hn[19];
   int e;
   if constexpr (BASIS == 0) {
-    e = collide3_fnorm<R>(h, C, d.k0, d.k1, d.noise, site, t, &park[0][threadIdx.x], hn);
+    e = collide3_fnorm<R>(h, C, d.noise, Nu, &park[0][threadIdx.x], hn);
   } else {
-    e = collide3_hermite<R>(h, C, d.k0, d.k1, d.noise, site, t);
+    e = collide3_hermite<R, !kEarlyNoise>(h, C, d.noise, Nu, d.k0, d.k1, cell(x, y, z, d), t);
 #pragma unroll
     for (int i = 0; i < 19; ++i) hn[i] = h[i];
   }
