@@ -35,7 +35,10 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"f32": 72, "f64": 144}
 # D3Q19 FP32 f-norm step: VALU wavefront instructions per wavefront (= per
 # site), profiles/step3_fp32_256cube_d3q19.md
-D3Q19_VALU_PER_SITE = 2482
+D3Q19_VALU_PER_SITE = 2517
+# VALU issue peak: 256 CUs x 4 SIMDs, one wavefront instruction (64 lanes,
+# 16 per cycle) every 4 cycles at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 # sources of the step kernel (the one whose HBM traffic the profiles record)
 KERNEL_SOURCES = ["paper_1204_6734_amd/csrc/flb_device.hpp",
                   "paper_1204_6734_amd/csrc/flb_buffer.hpp",
@@ -261,16 +264,22 @@ def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256):
     kernel_ms = kms / max(launches, 1)
     achieved = 152 * sites / (kernel_ms * 1e-3) / 1e9
     # the kernel is bound by VALU issue: wavefront instructions per site from
-    # the SQ_INSTS_VALU / SQ_WAVES counters of the profile summary, at four
-    # cycles per wavefront instruction on 1024 SIMDs at 2.4 GHz
-    issue_ms = D3Q19_VALU_PER_SITE * sites / 64 * 4 / 1024 / 2.4e9 * 1e3
+    # the SQ_INSTS_VALU / SQ_WAVES counters of the profile summary (one
+    # wavefront instruction serves 64 sites), against the issue peak
+    wave_instr = D3Q19_VALU_PER_SITE * sites / 64
+    issue_ms = wave_instr / VALU_ISSUE_PEAK * 1e3
+    rate = wave_instr / (kernel_ms * 1e-3) / 1e9
     return {"mlups": sites * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps,
             "kernel_ms": kernel_ms, "sites": sites, "steps": steps,
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "bytes_per_site": 152, "kernel": "step3_kernel<float,float,fnorm>"},
-            "valu": {"per_site": D3Q19_VALU_PER_SITE, "issue_bound_ms": round(issue_ms, 4),
-                     "kernel_over_issue_bound": round(kernel_ms / issue_ms, 4)}}
+            "roofline": {"bound": "alu", "achieved": round(rate, 1),
+                         "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+                         "unit": "G wavefront VALU instructions/s",
+                         "frac": round(rate * 1e9 / VALU_ISSUE_PEAK, 4),
+                         "valu_per_site": D3Q19_VALU_PER_SITE,
+                         "issue_bound_ms": round(issue_ms, 4),
+                         "kernel": "step3_kernel<float,float,fnorm>"},
+            "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_site": 152}}
 
 
 def copy_calibration(reps: int = 5):

@@ -39,3 +39,46 @@ def test_cpu_baseline_record():
     r = bench.cpu_baseline(seconds=0.5)
     assert r["kind"] == "oracle" and r["unit"] == "MLUPS" and r["cores"] == 1
     assert r["value"] > 0 and "128x128" in r["sample"]
+
+
+def test_d3q19_line_reports_the_issue_roofline():
+    """The D3Q19 workload is bound by VALU issue: its roofline object is
+    measured against the issue peak of 1024 SIMDs at 2.4 GHz (one wavefront
+    instruction per 4 cycles), with the HBM fraction beside it."""
+    class Lat:
+        def __init__(self, p, stream=None):
+            pass
+
+        def step(self, n):
+            pass
+
+        def sync(self):
+            pass
+
+        def profile(self, on):
+            pass
+
+        def kernel_time(self):
+            return 10.0, 10  # 1 ms per launch
+
+    class F:
+        FP32_SHIFTED = 1
+        Lattice3 = Lat
+
+        @staticmethod
+        def make_params3(*a, **k):
+            return None
+
+    class Torch:
+        class cuda:
+            @staticmethod
+            def current_stream():
+                return None
+
+    r = bench.run_d3q19(F, Torch, steps=10, warmup=1, n=64)
+    rf, hb = r["roofline"], r["hbm"]
+    assert bench.VALU_ISSUE_PEAK == 614.4e9
+    wave_instr = bench.D3Q19_VALU_PER_SITE * 64 ** 3 / 64
+    assert rf["bound"] == "alu" and abs(rf["achieved"] - wave_instr / 1e-3 / 1e9) < 0.1
+    assert abs(rf["frac"] - rf["issue_bound_ms"] / 1.0) < 1e-3
+    assert abs(hb["achieved"] - 152 * 64 ** 3 / 1e-3 / 1e9) < 0.1
