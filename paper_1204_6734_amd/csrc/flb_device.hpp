@@ -235,15 +235,17 @@ __device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint32_
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 // FP64 1/sqrt(x) and 1/x: the hardware estimates refined by Newton-Raphson
-// (three steps for the square root, each at least doubling the correct bits
-// of the estimate; two for the reciprocal), to within a few ulp of the
-// correctly rounded values at a fraction of the cost of sqrt and divide.
-// Arguments are positive and finite here (pivots and densities).
+// to within a few ulp of the correctly rounded values, at a fraction of the
+// cost of sqrt and divide.  The gfx950 estimates are good to 2^-24 relative
+// (measured on 4M arguments over [2^-20, 2^20]); a step squares the relative
+// error (times 1.5 for the square root), so two steps reach the FP64
+// rounding level for both.  Arguments are positive and finite here (pivots
+// and densities).
 __device__ __forceinline__ double rsqrt_t(double x) {
   double r = __builtin_amdgcn_rsq(x);
   const double hx = 0.5 * x;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) r = fma(r, fma(-hx * r, r, 0.5), r);
+  for (int k = 0; k < 2; ++k) r = fma(r, fma(-hx * r, r, 0.5), r);
   return r;
 }
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
