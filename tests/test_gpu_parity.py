@@ -115,11 +115,12 @@ def test_fp32_shifted_moments_match_fp64_oracle(flb, ux0):
     assert worst <= 1e-5, worst
 
 
-@pytest.mark.parametrize("basis", ["fnorm", "lut"])
+@pytest.mark.parametrize("basis", ["fnorm", "hermite", "lut"])
 def test_fp32_storage_fp64_compute_matches_oracle(flb, basis):
     """|u0| above 0.25: FP32-shifted storage with the collision computed in
     FP64 (the large-velocity path), against the oracle after 1000 steps."""
-    b = {"fnorm": flb.BASIS_FNORM_LOCAL, "lut": flb.BASIS_FNORM_LUT}[basis]
+    b = {"fnorm": flb.BASIS_FNORM_LOCAL, "hermite": flb.BASIS_HERMITE,
+         "lut": flb.BASIS_FNORM_LUT}[basis]
     nx, ny = 100, 30
     kw = dict(ux0=0.3, uy0=0.1, kT=1e-4, tau=TAUS, seed=12)
     g, o = both(flb, nx, ny, flb.FP32_SHIFTED, basis=b, **kw)
@@ -128,6 +129,29 @@ def test_fp32_storage_fp64_compute_matches_oracle(flb, basis):
     mg, mo = g.moments(flb.AT_U0), o.moments(flb.AT_U0)
     worst = max(np.abs(mg[a] - mo[a]).max() / np.abs(mo[a]).max() for a in range(9))
     assert worst <= 1e-5, worst
+
+
+@pytest.mark.parametrize("ux0", [0.1, 0.3])
+def test_fp32_covariance_sums_match_oracle(flb, ux0):
+    """FP32-shifted storage (FP32 and, at u0 = 0.3, FP64 collisions): the
+    correlator sums, staged in FP32 and summed on the matrix cores, against
+    the oracle's FP64 run of the same noise.  The stored deviations h carry
+    one FP32 rounding (2^-24 relative) and the dissipative update does not
+    amplify it, so the covariances, products of two deviations, agree to a
+    few 1e-7 of their largest entry (bound 1e-6); the means, sums of
+    deviations that nearly cancel, to 1e-5 of their largest entry (measured
+    8e-9 / 5e-8 and 1.2e-6 / 6e-7)."""
+    kw = dict(ux0=ux0, kT=1e-4, tau=TAUS, seed=5, sample_every=1, block_steps=50)
+    g, o = both(flb, 40, 24, flb.FP32_SHIFTED, **kw)
+    g.step(300)
+    o.step(300)
+    cg, co = g.covariance(), o.covariance()
+    assert cg["nsamples"] == co["nsamples"] == 300 * 40 * 24
+    scale = np.abs(co["cov_f"]).max()
+    err = np.abs(cg["cov_f"] - co["cov_f"]).max() / scale
+    merr = np.abs(cg["mean_df"] - co["mean_df"]).max() / np.abs(co["mean_df"]).max()
+    print(f"u0 {ux0}: cov_f rel err {err:.2e}, mean_df rel err {merr:.2e}")
+    assert err <= 1e-6 and merr <= 1e-5, (err, merr)
 
 
 def test_covariance_sums_match_oracle(flb):
