@@ -215,3 +215,26 @@ def test_server_failing_request_leaves_the_others_unchanged(flb):
         alone = _serve(flb, [reqs[k]], 64 << 20, slots=1, chunk=20)[0]
         assert mix[k]["status"] == alone["status"] == 0
         np.testing.assert_array_equal(mix[k]["cov"]["cov_f"], alone["cov"]["cov_f"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_server_odd_step_count_equals_lattice(flb, prec):
+    """A request of an odd number of steps (the server's chunks are even, so
+    it stops inside a chunk) with time blocks that end inside chunks: its
+    correlators equal the single lattice's bit for bit, in both storage
+    precisions."""
+    precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+    kw = dict(precision=precision, ux0=0.1, kT=1e-4, tau=I.mixed_taus(2), seed=21,
+              sample_every=1, block_steps=7)
+    p = flb.make_params(29, 13, **kw)  # 1 x 4 tiles
+    L = flb.Lattice(p)
+    L.step(301)
+    c = L.covariance()
+    S = flb.Server(64 << 20, max_slots=2, chunk_steps=10, precision=precision, threaded=False)
+    S.submit(p, 301, tag=1)
+    S.drain()
+    r = S.poll(4)[0]
+    S.close()
+    assert r["status"] == 0 and r["cov"]["nsamples"] == c["nsamples"] == 301 * 29 * 13
+    np.testing.assert_array_equal(r["cov"]["cov_f"], c["cov_f"])
+    np.testing.assert_array_equal(r["cov"]["mean_df"], c["mean_df"])
