@@ -1,10 +1,11 @@
 #!/usr/bin/env python3
 """Benchmark of the fused fluctuating D2Q9 step (f-norm basis) on one GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|ensemble|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload large|ensemble|serve|paper|d3q19]
 
 Default workload ("large"): one 8192 x 8192 periodic lattice, FP32 storage
-shifted by w_i rho0, rho0 = 1, u_x0 = 0.1, kT = 1e-4, all tau = 1, initial
+shifted by f^0(rho0, u0), rho0 = 1, u_x0 = 0.1, kT = 1e-4, all tau = 1, initial
 transverse shear wave u_y = 1e-3 sin(2 pi x / L).  One step is the whole
 hot path: the fused collide-and-stream kernel over all sites; every 100
 steps the structure factor of rho, j~_x, j~_y is sampled (2-D FFT) and the
