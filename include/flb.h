@@ -68,7 +68,7 @@ typedef enum {
 /* Parameters of one lattice. */
 typedef struct {
   int32_t nx, ny;       /* periodic sides, each >= 3                              */
-  double rho0;          /* reference density (> 0); FP32 storage keeps f - w rho0  */
+  double rho0;          /* reference density (> 0); storage keeps f - f^0(rho0,u0) */
   double ux0, uy0;      /* background velocity (inside the validity region)       */
   double kT;            /* noise temperature (>= 0); mu = 3 kT                    */
   double tau[6];        /* relaxation times of modes 3..8 (Pi_xx-yy, Pi_xy,

@@ -7,7 +7,7 @@
 // structure-factor fields of eqs. (24)-(26) fused in when a sample is due.
 //
 // Memory layout: one population array per lattice, structure of arrays
-// [9][ny][nx] of shifted values h_i = f_i - w_i rho0 (FP32 or FP64), updated
+// [9][ny][nx] of shifted values h_i = f_i - f_i^0(rho0, u0) (FP32 or FP64), updated
 // in place with the two-phase "AA" access pattern: on even steps a site
 // reads its own nine slots and writes the post-collision values back
 // reversed; on odd steps it reads the reversed values of its neighbours and
