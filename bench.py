@@ -94,13 +94,15 @@ def cpu_baseline(seconds: float = 12.0, basis: int = 0, ux0: float = 0.1) -> dic
 
 
 def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 100,
-              launch=None, basis: str = "fnorm", precision: str = "fp32", ux0: float = 0.1):
+              launch=None, basis: str = "fnorm", precision: str = "fp32", ux0: float = 0.1,
+              sample_every: int = 0):
     from paper_1204_6734_amd import inputs as I
     stream = torch.cuda.current_stream()
     bname, bcode = BASES[basis]
     fp32 = precision == "fp32"
     p = F.make_params(nx, nx, precision=F.FP32_SHIFTED if fp32 else F.FP64, basis=bcode,
-                      rho0=1.0, ux0=ux0, kT=1e-4, seed=1, init=F.INIT_FIELDS, sk_every=every)
+                      rho0=1.0, ux0=ux0, kT=1e-4, seed=1, init=F.INIT_FIELDS, sk_every=every,
+                      sample_every=sample_every, block_steps=100 if sample_every > 0 else 0)
     L = F.Lattice(p, stream=stream)
     L.set_fields(*I.shear_wave_fields(nx, nx, ux0=ux0, amp=1e-3))
     if launch is None:
@@ -142,16 +144,22 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                                    f"rho0=1, u_x0={ux0:g}, kT=1e-4, "
                                    f"tau=1, shear wave 1e-3 sin(2 pi x/L); " +
                                    (f"S(k) and j~_y(2 pi/L) every {every} steps" if every > 0
-                                    else "no S(k), no mode log"),
+                                    else "no S(k), no mode log") +
+                                   (f"; correlators every {sample_every} steps"
+                                    if sample_every > 0 else ""),
                        "nx": nx, "ny": nx, "precision": "fp32_shifted" if fp32 else "fp64",
-                       "basis": bname, "sk_every": every, "parallelism": "single GPU"},
+                       "basis": bname, "sk_every": every, "sample_every": sample_every,
+                       "parallelism": "single GPU"},
             "dtype": "f32" if fp32 else "f64",
             # FP32 storage computes the collision in FP64 above |u0| = 0.25
             "kernel_label": "step_kernel<%s,%s>" % (
                 ("float,float" if abs(ux0) <= 0.25 else "float,double") if fp32
-                else "double,double", bname),
+                else "double,double", bname) +
+                (f" (correlator-sampling variant every {sample_every} steps)"
+                 if sample_every > 0 else ""),
             "kernel_name": f"step_{precision}_{nx}" + ("" if basis == "fnorm" else f"_{basis}") +
-                           ("_fp64compute" if fp32 and abs(ux0) > 0.25 else "")}
+                           ("_fp64compute" if fp32 and abs(ux0) > 0.25 else "") +
+                           (f"_sample{sample_every}" if sample_every > 0 else "")}
 
 
 def run_ensemble(F, torch, steps: int, warmup: int, n: int = 64, side: int = 128,
@@ -321,6 +329,8 @@ def main():
     ap.add_argument("--ux0", type=float, default=0.1,
                     help="background velocity of the large workload (above 0.25 the FP32-storage "
                          "collision runs in FP64)")
+    ap.add_argument("--sample-every", type=int, default=0,
+                    help="correlator sampling interval of the large workload (0: off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -362,7 +372,8 @@ def main():
         return
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     r = run_large(F, torch, args.steps, args.warmup, nx=args.nx, every=args.sk_every,
-                  launch=launch, basis=args.basis, precision=args.precision, ux0=args.ux0)
+                  launch=launch, basis=args.basis, precision=args.precision, ux0=args.ux0,
+                  sample_every=args.sample_every)
     mlups = r["sites"] * args.steps / r["dt"] / 1e6
     bps = BYTES_PER_SITE[r["dtype"]]
     achieved = bps * r["sites"] / (r["kernel_ms"] * 1e-3) / 1e9
