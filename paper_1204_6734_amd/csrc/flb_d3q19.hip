@@ -18,6 +18,7 @@
 #include "flb_buffer.hpp"
 #include "flb_d3q19.hpp"
 #include "flb_device.hpp"
+#include "flb_reduce.hpp"
 
 namespace flb {
 namespace d3q19 {
@@ -613,32 +614,14 @@ __global__ void io3_kernel(S* pop, double* f, Desc3 d, int odd, int to_storage) 
   }
 }
 
-// Time blocks of the correlator sums (nstat values per record).
-__global__ void close_block3_kernel(double* partials, int ntiles, double* record) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= kNStat3) return;
-  double s = 0.0;
-  for (int t = 0; t < ntiles; ++t) {
-    s += partials[(size_t)t * kNStat3 + v];
-    partials[(size_t)t * kNStat3 + v] = 0.0;
-  }
-  record[v] = s;
-}
-
+// Time blocks of the correlator sums (kNStat3 values per record); closing a
+// block and the open sums: flb_reduce.hpp.
 __global__ void merge_blocks3_kernel(double* rec, int nhalf) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= kNStat3) return;
   for (int b = 0; b < nhalf; ++b)
     rec[(size_t)b * kNStat3 + v] =
         rec[(size_t)(2 * b) * kNStat3 + v] + rec[(size_t)(2 * b + 1) * kNStat3 + v];
-}
-
-__global__ void open_sum3_kernel(const double* partials, int ntiles, double* out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= kNStat3) return;
-  double s = 0.0;
-  for (int t = 0; t < ntiles; ++t) s += partials[(size_t)t * kNStat3 + v];
-  out[v] = s;
 }
 
 __global__ void fill3_kernel(double* p, size_t n) {
@@ -686,16 +669,14 @@ hipError_t launch_io3(int storage, void* pop, double* f, const Desc3& d, int odd
 }
 
 hipError_t launch_close_block3(double* partials, int ntiles, double* record, hipStream_t st) {
-  hipLaunchKernelGGL(close_block3_kernel, dim3(1), dim3(256), 0, st, partials, ntiles, record);
-  return hipGetLastError();
+  return close_block_sums<kNStat3>(partials, ntiles, record, st);
 }
 hipError_t launch_merge_blocks3(double* rec, int nhalf, hipStream_t st) {
   hipLaunchKernelGGL(merge_blocks3_kernel, dim3(1), dim3(256), 0, st, rec, nhalf);
   return hipGetLastError();
 }
 hipError_t launch_open_sum3(const double* partials, int ntiles, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(open_sum3_kernel, dim3(1), dim3(256), 0, st, partials, ntiles, out);
-  return hipGetLastError();
+  return open_sums<kNStat3>(partials, ntiles, out, st);
 }
 hipError_t launch_fill3(double* p, size_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;

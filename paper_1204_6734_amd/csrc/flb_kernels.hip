@@ -9,6 +9,7 @@
 
 #include "flb_device.hpp"
 #include "flb_kernels.hpp"
+#include "flb_reduce.hpp"
 
 namespace flb {
 
@@ -211,18 +212,7 @@ __global__ void fourier_mode_kernel(const S* __restrict__ pop, double2* partial,
 }
 
 // ------------------------------------------------------------ time blocks
-// Close the open time block of a lattice: record[slot] = sum over tiles of
-// the partials (fixed order), then clear the partials.
-__global__ void close_block_kernel(double* partials, int ntiles, double* record) {
-  const int v = threadIdx.x;
-  if (v >= kNStat) return;
-  double s = 0.0;
-  for (int t = 0; t < ntiles; ++t) {
-    s += partials[(size_t)t * kNStat + v];
-    partials[(size_t)t * kNStat + v] = 0.0;
-  }
-  record[v] = s;
-}
+// Closing a block and the open sums: flb_reduce.hpp.
 
 // Neighbouring records merge pairwise: rec[b] = rec[2b] + rec[2b+1].
 __global__ void merge_blocks_kernel(double* rec, int nhalf) {
@@ -231,15 +221,6 @@ __global__ void merge_blocks_kernel(double* rec, int nhalf) {
   for (int b = 0; b < nhalf; ++b)
     rec[(size_t)b * kNStat + v] = rec[(size_t)(2 * b) * kNStat + v] +
                                   rec[(size_t)(2 * b + 1) * kNStat + v];
-}
-
-// Sum of the open partials (fixed order) into out[kNStat].
-__global__ void open_sum_kernel(const double* partials, int ntiles, double* out) {
-  const int v = threadIdx.x;
-  if (v >= kNStat) return;
-  double s = 0.0;
-  for (int t = 0; t < ntiles; ++t) s += partials[(size_t)t * kNStat + v];
-  out[v] = s;
 }
 
 __global__ void fill_kernel(double* p, size_t n, double value) {
@@ -577,8 +558,7 @@ hipError_t launch_fourier_mode(int storage, const void* pop, double2* partial, i
 }
 
 hipError_t launch_close_block(double* partials, int ntiles, double* record, hipStream_t st) {
-  hipLaunchKernelGGL(close_block_kernel, dim3(1), dim3(64), 0, st, partials, ntiles, record);
-  return hipGetLastError();
+  return close_block_sums<kNStat>(partials, ntiles, record, st);
 }
 
 hipError_t launch_merge_blocks(double* rec, int nhalf, hipStream_t st) {
@@ -587,8 +567,7 @@ hipError_t launch_merge_blocks(double* rec, int nhalf, hipStream_t st) {
 }
 
 hipError_t launch_open_sum(const double* partials, int ntiles, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(open_sum_kernel, dim3(1), dim3(64), 0, st, partials, ntiles, out);
-  return hipGetLastError();
+  return open_sums<kNStat>(partials, ntiles, out, st);
 }
 
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st) {
