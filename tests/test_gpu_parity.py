@@ -154,6 +154,23 @@ def test_fp32_covariance_sums_match_oracle(flb, ux0):
     assert err <= 1e-6 and merr <= 1e-5, (err, merr)
 
 
+def test_time_blocks_of_many_tiles_match_oracle(flb):
+    """Closing a time block folds ranges of tiles in parallel: 520 x 140 is
+    9 x 35 = 315 tiles, so ranges hold two tiles and the last one is short.
+    Five blocks close in 50 samples; sums and standard errors against the
+    oracle's serial ones."""
+    kw = dict(ux0=0.1, kT=1e-4, tau=TAUS, seed=17, sample_every=1, block_steps=10)
+    g, o = both(flb, 520, 140, flb.FP64, **kw)
+    g.step(50)
+    o.step(50)
+    cg, co = g.covariance(), o.covariance()
+    assert cg["nsamples"] == co["nsamples"] == 50 * 520 * 140
+    assert cg["nblocks"] == co["nblocks"] == 5
+    for key in ("cov_f", "cov_m_fnorm_u0", "se_cov_f"):
+        err = np.abs(cg[key] - co[key]).max() / np.abs(co[key]).max()
+        assert err <= 1e-10, (key, err)
+
+
 def test_covariance_sums_match_oracle(flb):
     kw = dict(ux0=0.1, kT=1e-4, tau=TAUS, seed=5, sample_every=1, block_steps=50)
     g, o = both(flb, 40, 24, flb.FP64, **kw)
