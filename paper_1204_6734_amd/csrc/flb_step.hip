@@ -83,6 +83,21 @@ constexpr int kSampleTilesPerBlock = 2;
 
 typedef double double4_v __attribute__((ext_vector_type(4)));
 
+// Position of statistic v in a wavefront's 16 x 16 result X^T X (row-major):
+// the sum of df_i is entry (i, 9), the product df_i df_j (i <= j) entry (i, j).
+struct StatPos {
+  int pos[kNStat];
+};
+constexpr StatPos stat_positions() {
+  StatPos p{};
+  int q = 0;
+  for (int i = 0; i < 9; ++i) p.pos[q++] = i * 16 + 9;
+  for (int i = 0; i < 9; ++i)
+    for (int j = i; j < 9; ++j) p.pos[q++] = i * 16 + j;
+  return p;
+}
+__constant__ StatPos kStatPos = stat_positions();
+
 // Correlator sums of df_i = f_i - f_i^0(rho0, u0) (= the stored h_i): 9
 // first moments and the 45 products i <= j (row-major), added to this
 // tile's open time-block partials.  For one wavefront (64 sites) these are
@@ -91,20 +106,26 @@ typedef double double4_v __attribute__((ext_vector_type(4)));
 // sites per instruction) after the wavefront has staged its values in LDS,
 // where lane l picks column l % 16 of site l / 16 of each group of four.  The
 // instruction leaves output row l / 16 + 4 r, column l % 16 in element r of
-// lane l.  The four wavefronts of the tile then add their sums in a fixed
-// order, so a tile's partial does not depend on the workgroup shape.  Every
-// thread of the workgroup calls this (it holds two workgroup barriers);
-// `due` is uniform over one tile and says whether the tile samples at all.
-// Sites outside the lattice stage zeros.
+// lane l; the wavefront writes the 16 x 16 result over its staged values.
+// The four wavefronts of the tile then add their results in a fixed order,
+// so a tile's partial does not depend on the workgroup shape.  Every thread
+// of the workgroup calls this (it holds two workgroup barriers); `due` is
+// uniform over one tile and says whether the tile samples at all.  Sites
+// outside the lattice stage zeros.
 template <typename S, typename R>
 __device__ __forceinline__ void sample_correlators(const R h[9], bool active, bool due,
                                                    double* __restrict__ partials, int sub,
                                                    int wave) {
-  __shared__ S xs[kSampleTilesPerBlock][kTileY][kTileX * 9];
-  __shared__ double red[kSampleTilesPerBlock][kTileY][kTileX];
+  // per wavefront: 64 x 9 staged values, then its 16 x 16 FP64 result
+  constexpr int kWaveBytes = kTileX * 9 * (int)sizeof(S);
+  static_assert(kWaveBytes >= 16 * 16 * (int)sizeof(double), "result fits the staging area");
+  __shared__ double xs[kSampleTilesPerBlock][kTileY][kWaveBytes / sizeof(double)];
   const int lane = threadIdx.x & 63;
+  const int v = threadIdx.x & (kBlock - 1);
+  const bool adds = due && v < kNStat;
+  const int pos = adds ? kStatPos.pos[v] : 0;
   if (due) {
-    S* x = xs[sub][wave];
+    S* x = reinterpret_cast<S*>(xs[sub][wave]);
 #pragma unroll
     for (int i = 0; i < 9; ++i) x[lane * 9 + i] = active ? (S)h[i] : S(0);
     // the values come back from other lanes of the same wavefront, whose LDS
@@ -118,28 +139,25 @@ __device__ __forceinline__ void sample_correlators(const R h[9], bool active, bo
     S xv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) xv[q] = x[(4 * q + grp) * 9 + colr];
+    // the result is written over the staged values: every read above is
+    // issued first (the compiler may not move the writes before them)
+    asm volatile("" ::: "memory");
     double4_v acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const double v = col < 9 ? (double)xv[q] : pad;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+      const double val = col < 9 ? (double)xv[q] : pad;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
     }
-    // row i = grp + 4 r, column col: sum_i = (i, 9), product (i, j <= 8) for i <= j
+    double* out = xs[sub][wave];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = grp + 4 * r;
-      if (i < 9 && col == 9) red[sub][wave][i] = acc[r];
-      if (i < 9 && col < 9 && i <= col)
-        red[sub][wave][9 + 9 * i - (i * (i - 1)) / 2 + (col - i)] = acc[r];
-    }
+    for (int r = 0; r < 4; ++r) out[(grp + 4 * r) * 16 + col] = acc[r];
   }
   __syncthreads();
-  const int v = threadIdx.x & (kBlock - 1);
-  if (due && v < kNStat) {
-    const double tot = (red[sub][0][v] + red[sub][1][v]) + (red[sub][2][v] + red[sub][3][v]);
+  if (adds) {
+    const double tot = (xs[sub][0][pos] + xs[sub][1][pos]) + (xs[sub][2][pos] + xs[sub][3][pos]);
     partials[v] += tot;
   }
-  __syncthreads();  // red and xs are reused by the next tile
+  __syncthreads();  // xs is reused by the next tile
 }
 
 // Byte offsets (within their planes) of the nine populations a site reads
