@@ -286,6 +286,11 @@ def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256):
                          "frac": round(rate * 1e9 / VALU_ISSUE_PEAK, 4),
                          "valu_per_site": D3Q19_VALU_PER_SITE,
                          "issue_bound_ms": round(issue_ms, 4),
+                         "model": "SQ_INSTS_VALU per wavefront at one wavefront instruction "
+                                  "per 4 cycles per SIMD, 1024 SIMDs, 2.4 GHz; instructions "
+                                  "that do not hold the VALU for 4 cycles (transcendentals "
+                                  "go to their own unit) let frac exceed 1 by a few %: "
+                                  "frac near 1 means bound by VALU issue",
                          "kernel": "step3_kernel<float,float,fnorm>"},
             "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_site": 152}}
