@@ -287,10 +287,10 @@ def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256):
                          "valu_per_site": D3Q19_VALU_PER_SITE,
                          "issue_bound_ms": round(issue_ms, 4),
                          "model": "SQ_INSTS_VALU per wavefront at one wavefront instruction "
-                                  "per 4 cycles per SIMD, 1024 SIMDs, 2.4 GHz; instructions "
-                                  "that do not hold the VALU for 4 cycles (transcendentals "
-                                  "go to their own unit) let frac exceed 1 by a few %: "
-                                  "frac near 1 means bound by VALU issue",
+                                  "per 4 cycles per SIMD, 1024 SIMDs, 2.4 GHz; the model "
+                                  "charges every instruction a full VALU slot (transcendentals "
+                                  "issue to their own unit), so frac can exceed 1 (1.00-1.07 "
+                                  "measured): frac near 1 means bound by VALU issue",
                          "kernel": "step3_kernel<float,float,fnorm>"},
             "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_site": 152}}
