@@ -23,8 +23,6 @@ namespace flb {
 
 static size_t storage_size(int storage) { return storage == 0 ? sizeof(double) : sizeof(float); }
 
-static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
-
 // Lay out every device array of the group in `a` (a.base may be null to
 // size it).
 void Group::layout(Arena& a) {
