@@ -86,6 +86,8 @@ def lib():
                                            C.POINTER(C.c_uint32)]
         L.flbref_site_gaussians.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, d]
         L.flbref_collide.argtypes = [C.POINTER(Params), d, C.c_uint64, C.c_uint64, d]
+        L.flbref_collide_lut_at.argtypes = [C.POINTER(Params), d, C.c_uint64, C.c_uint64,
+                                            C.c_int32, C.c_int32, d]
         L.flbref_lattice_create.argtypes = [C.POINTER(Params), C.POINTER(C.c_void_p)]
         L.flbref_lattice_set_fields.argtypes = [C.c_void_p, d, d, d]
         L.flbref_lattice_set_populations.argtypes = [C.c_void_p, d, C.c_uint64]
@@ -184,6 +186,15 @@ def collide(p: Params, f, site: int = 0, step: int = 0) -> np.ndarray:
     fi = np.ascontiguousarray(f, dtype=np.float64)
     fo = np.zeros(9)
     _check(lib().flbref_collide(C.byref(p), _dp(fi), site, step, _dp(fo)), "collide")
+    return fo
+
+
+def collide_lut_at(p: Params, f, ix: int, iy: int, site: int = 0, step: int = 0) -> np.ndarray:
+    """Table-basis collision with the basis at grid point (ix, iy) * 0.02."""
+    fi = np.ascontiguousarray(f, dtype=np.float64)
+    fo = np.zeros(9)
+    _check(lib().flbref_collide_lut_at(C.byref(p), _dp(fi), site, step, ix, iy, _dp(fo)),
+           "collide_lut_at")
     return fo
 
 

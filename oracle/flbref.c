@@ -214,8 +214,30 @@ static const uint32_t TAG_THERMAL = 0x80000000u;
  *     eq. (18)).
  * For the conserved modes the bracket vanishes identically, so the sum
  * runs over a = 3..8. */
+static int collide_with(const flbref_params* p, const double f[9], uint64_t site,
+                        uint64_t step, const int32_t* grid_point, double fout[9]);
+
 int flbref_collide(const flbref_params* p, const double f[9], uint64_t site, uint64_t step,
                    double fout[9]) {
+  return collide_with(p, f, site, step, NULL, fout);
+}
+
+/* The table variant's collision with its basis taken at the grid point
+ * u_g = (ix, iy) * 0.02 instead of the nearest one.  A local velocity that
+ * lies exactly half-way between two grid points has two nearest points;
+ * flbref_collide takes floor(u / 0.02 + 1/2), and this call gives the
+ * collision at the other one, so that either reading can be checked. */
+int flbref_collide_lut_at(const flbref_params* p, const double f[9], uint64_t site,
+                          uint64_t step, int32_t ix, int32_t iy, double fout[9]) {
+  if (p->basis != FLBREF_BASIS_FNORM_LUT) return FLBREF_E_ARG;
+  if (ix < -LUT_HALF || ix > LUT_HALF || iy < -LUT_HALF || iy > LUT_HALF)
+    return FLBREF_E_INVALID_VELOCITY;
+  const int32_t g[2] = {ix, iy};
+  return collide_with(p, f, site, step, g, fout);
+}
+
+static int collide_with(const flbref_params* p, const double f[9], uint64_t site,
+                        uint64_t step, const int32_t* grid_point, double fout[9]) {
   double rho = 0.0, jx = 0.0, jy = 0.0;
   for (int i = 0; i < 9; ++i) {
     rho += f[i];
@@ -241,7 +263,13 @@ int flbref_collide(const flbref_params* p, const double f[9], uint64_t site, uin
     Meq[6] = Meq[7] = Meq[8] = 0.0;
   } else if (p->basis == FLBREF_BASIS_FNORM_LUT) {
     double ug[2], g[9];
-    int rc = lut_point(ux, uy, ug);
+    int rc = FLBREF_OK;
+    if (grid_point) {
+      ug[0] = grid_point[0] * LUT_DU;
+      ug[1] = grid_point[1] * LUT_DU;
+    } else {
+      rc = lut_point(ux, uy, ug);
+    }
     if (rc != FLBREF_OK) return rc;
     unit_weight(ug[0], ug[1], g);
     rc = gram_schmidt(g, mt);

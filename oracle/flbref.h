@@ -75,6 +75,9 @@ void flbref_site_gaussians(uint64_t seed, uint64_t site, uint64_t step, uint32_t
 int flbref_collide(const flbref_params* p, const double f[9], uint64_t site, uint64_t step,
                    double fout[9]);
 int flbref_lut_basis(double ux, double uy, double mt[81], double ug[2]);
+/* Table-variant collision at grid point (ix, iy) * 0.02, |ix|, |iy| <= 25. */
+int flbref_collide_lut_at(const flbref_params* p, const double f[9], uint64_t site,
+                          uint64_t step, int32_t ix, int32_t iy, double fout[9]);
 
 /* ---- lattice ---- */
 int flbref_lattice_create(const flbref_params* p, flbref_lattice** out);
