@@ -383,10 +383,15 @@ def main():
     bps = BYTES_PER_SITE[r["dtype"]]
     achieved = bps * r["sites"] / (r["kernel_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profiles(r["kernel_name"])
-    # the same traffic with no arithmetic (as many 4-byte planes as the step
-    # reads: 9 in FP32, 18 in FP64): the practical ceiling on this device
-    copy_ms = F.copy_probe(bps // 8, r["sites"], reps=20)
+    # the step's memory traffic with no arithmetic (same layout, tiles and
+    # addressing): the practical ceiling of its access pattern; and a plain
+    # contiguous copy of the population bytes: the device's streaming ceiling
+    fp32 = r["dtype"] == "f32"
+    copy_ms = F.copy_probe(args.nx, args.nx, F.FP32_SHIFTED if fp32 else F.FP64, reps=20)
     copy_gbps = bps * r["sites"] / (copy_ms * 1e-3) / 1e9
+    stream_bytes = bps // 2 * r["sites"]
+    stream_ms = F.stream_copy_probe(stream_bytes, reps=20)
+    stream_gbps = 2 * stream_bytes / (stream_ms * 1e-3) / 1e9
     out = {
         "metric": "fluct. D2Q9 MLUPS, % of HBM roofline; served solves/s + p99 latency",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -400,7 +405,12 @@ def main():
                      "launches": r["launches"],
                      "copy_probe": {"GBps": round(copy_gbps, 1), "ms": round(copy_ms, 4),
                                     "frac_of_peak": round(copy_gbps / HBM_PEAK_GBS, 4),
-                                    "kernel_frac_of_copy": round(achieved / copy_gbps, 4)}},
+                                    "kernel_frac_of_copy": round(achieved / copy_gbps, 4),
+                                    "what": "the step's loads and stores, no arithmetic"},
+                     "stream_copy": {"GBps": round(stream_gbps, 1), "ms": round(stream_ms, 4),
+                                     "frac_of_peak": round(stream_gbps / HBM_PEAK_GBS, 4),
+                                     "what": "contiguous copy of the population bytes, "
+                                             "16 B per thread"}},
         "pct_hbm_roofline": round(100 * mlups * 1e6 * bps / (HBM_PEAK_GBS * 1e9), 2),
         "launch": r["launch"],
     }

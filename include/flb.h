@@ -191,16 +191,26 @@ void flb_lattice_destroy(flb_lattice* L);
 /* Message of the last failed call on this thread (never NULL). */
 const char* flb_last_error(void);
 
-/* Measurement utility, not part of the method: the device time of one copy
- * of nplanes (1..32) planes of plane_elems (< 2^32) 4-byte elements into a
- * second set of planes, with the step kernel's memory shape (each thread
- * reads one element of every plane, then writes them; coalesced, 256-thread
- * workgroups) and no arithmetic, averaged over reps (1..1000) copies after
- * three unmeasured ones.  The practical bandwidth ceiling of the step
- * kernel's traffic on the current device is 2 nplanes plane_elems 4 bytes
- * over that time.  Allocates and frees two buffers of nplanes plane_elems
- * 4 bytes on the current device; synchronises the device's null stream. */
-int flb_copy_probe(int32_t nplanes, uint64_t plane_elems, int32_t reps, double* ms_per_copy);
+/* Measurement utilities, not part of the method.
+ *
+ * flb_copy_probe: the device time of one pass of the step kernel's memory
+ * traffic with none of its arithmetic, over an nx x ny lattice of the given
+ * precision (flb_precision): the same storage layout, tiles, workgroup
+ * order and addressing, every site loading its nine values at a streaming
+ * phase and storing them back in place.  Averaged over reps (1..1000) pairs
+ * of an even and an odd pass after three unmeasured pairs.  18 values per
+ * site over that time is the practical bandwidth ceiling of the step's
+ * access pattern.  FLB_E_ARG for sizes flb_lattice_create rejects.
+ *
+ * flb_stream_copy_probe: the device time of one copy of `bytes` (a multiple
+ * of 16, below 2^40) between two contiguous buffers, 16 bytes per thread,
+ * averaged over reps (1..1000) copies after three unmeasured ones: the
+ * device's streaming ceiling, independent of any layout.
+ *
+ * Both allocate and free their buffers on the current device (FLB_E_OOM if
+ * that fails) and synchronise the device's null stream. */
+int flb_copy_probe(int32_t nx, int32_t ny, int32_t precision, int32_t reps, double* ms_per_pass);
+int flb_stream_copy_probe(uint64_t bytes, int32_t reps, double* ms_per_copy);
 
 /* ------------------------------------------------------------- ensembles
  * n replicas of one lattice shape (same nx, ny, precision, basis), each with

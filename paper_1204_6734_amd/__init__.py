@@ -144,7 +144,8 @@ _SIGS = {
     "flb3_lattice_reset_stats": [C.c_void_p],
     "flb3_lattice_profile": [C.c_void_p, C.c_int32],
     "flb3_lattice_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
-    "flb_copy_probe": [C.c_int32, C.c_uint64, C.c_int32, C.POINTER(C.c_double)],
+    "flb_copy_probe": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)],
+    "flb_stream_copy_probe": [C.c_uint64, C.c_int32, C.POINTER(C.c_double)],
     "flb_server_create": [C.POINTER(ServerConfig), C.c_void_p, C.POINTER(C.c_void_p)],
     "flb_server_submit": [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)],
     "flb_server_pump": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
@@ -445,11 +446,20 @@ class Ensemble(_Tunable):
         return ms.value, n.value
 
 
-def copy_probe(nplanes: int, plane_elems: int, reps: int = 20) -> float:
-    """Device time (ms) of one copy with the step kernel's memory shape and no
-    arithmetic (flb_copy_probe): the practical bandwidth ceiling."""
+def copy_probe(nx: int, ny: int, precision: int = FP32_SHIFTED, reps: int = 20) -> float:
+    """Device time (ms) of one pass of the step kernel's memory traffic with no
+    arithmetic over an nx x ny lattice (flb_copy_probe): the practical
+    ceiling of the step's access pattern."""
     ms = C.c_double()
-    _check(load().flb_copy_probe(nplanes, plane_elems, reps, C.byref(ms)), "copy_probe")
+    _check(load().flb_copy_probe(nx, ny, precision, reps, C.byref(ms)), "copy_probe")
+    return ms.value
+
+
+def stream_copy_probe(nbytes: int, reps: int = 20) -> float:
+    """Device time (ms) of one contiguous copy of nbytes, 16 bytes per thread
+    (flb_stream_copy_probe): the device's streaming ceiling."""
+    ms = C.c_double()
+    _check(load().flb_stream_copy_probe(nbytes, reps, C.byref(ms)), "stream_copy_probe")
     return ms.value
 
 

@@ -28,6 +28,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(void* pop, uint32_t
   return __builtin_amdgcn_make_buffer_rsrc(base, 0, N * (uint32_t)sizeof(S), 0x00020000);
 }
 
+// The same for one row of a row-interleaved array (the nine plane rows of
+// lattice row y, 9 pitch elements from element 9 y pitch): the plane goes in
+// the scalar offset, the column in the per-lane offset.
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void* pop, uint32_t pitch, int y) {
+  char* base = reinterpret_cast<char*>(pop) + (size_t)y * 9 * pitch * sizeof(S);
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, 9 * pitch * (uint32_t)sizeof(S), 0x00020000);
+}
+
 __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                           uint32_t soff, float*) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));

@@ -42,7 +42,7 @@ void Group::layout(Arena& a) {
   for (int s = 0; s < n; ++s) {
     const size_t N = (size_t)P[s].nx * P[s].ny;
     max_sites = std::max(max_sites, N);
-    pop[s] = a.take<char>(9 * N * storage_size(storage));
+    pop[s] = a.take<char>(population_elems(P[s].nx, P[s].ny) * storage_size(storage));
     if (P[s].sample_every > 0) {
       d_partials[s] = a.take<double>((size_t)hdesc[s].ntiles * kNStat);
       d_records[s] = a.take<double>((size_t)kMaxTimeBlocks * kNStat);
@@ -211,7 +211,7 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
     const double mu = p.init == FLB_INIT_THERMAL ? 3.0 * p.kT : 0.0;
     for (int y0 = 0; y0 < p.ny; y0 += band_rows) {
       const int rows = std::min(band_rows, p.ny - y0);
-      HIPC(launch_init(storage, pop[s], nullptr, nullptr, nullptr, p.rho0, p.ux0, p.uy0,
+      HIPC(launch_init(storage, pop[s], hdesc[s].pitch, nullptr, nullptr, nullptr, p.rho0, p.ux0, p.uy0,
                        slot_shift(hdesc[s]), p.nx, p.ny, mu, hdesc[s].k0, hdesc[s].k1, 0, y0, rows,
                        st));
     }
@@ -430,7 +430,7 @@ int Group::read_rows(int s, int y0, int nrows, double* f) {
   const size_t N = (size_t)p.nx * nrows;
   for (int b0 = y0; b0 < y0 + nrows; b0 += band_rows) {
     const int rows = std::min(band_rows, y0 + nrows - b0);
-    HIPC(launch_read_state(storage, pop[s], d_io, p.nx, p.ny, (int)(t & 1), slot_shift(hdesc[s]),
+    HIPC(launch_read_state(storage, pop[s], hdesc[s].pitch, d_io, p.nx, p.ny, (int)(t & 1), slot_shift(hdesc[s]),
                            b0, rows, st));
     const size_t B = (size_t)rows * p.nx;
     for (int i = 0; i < 9; ++i)
@@ -454,7 +454,7 @@ int Group::set_populations(int s, const double* f, uint64_t tnew) {
     for (int i = 0; i < 9; ++i)
       HIPC(hipMemcpyAsync(d_io + i * B, f + i * N + (size_t)y0 * p.nx, B * sizeof(double),
                           hipMemcpyHostToDevice, st));
-    HIPC(launch_write_state(storage, pop[s], d_io, p.nx, p.ny, (int)(t & 1), slot_shift(hdesc[s]),
+    HIPC(launch_write_state(storage, pop[s], hdesc[s].pitch, d_io, p.nx, p.ny, (int)(t & 1), slot_shift(hdesc[s]),
                             y0, rows, st));
     HIPC(hipStreamSynchronize(st));
   }
@@ -470,7 +470,7 @@ int Group::set_fields(int s, const double* rho, const double* ux, const double* 
     HIPC(hipMemcpyAsync(d_io, rho + off, B * sizeof(double), hipMemcpyHostToDevice, st));
     HIPC(hipMemcpyAsync(d_io + B, ux + off, B * sizeof(double), hipMemcpyHostToDevice, st));
     HIPC(hipMemcpyAsync(d_io + 2 * B, uy + off, B * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPC(launch_init(storage, pop[s], d_io, d_io + B, d_io + 2 * B, p.rho0, p.ux0, p.uy0,
+    HIPC(launch_init(storage, pop[s], hdesc[s].pitch, d_io, d_io + B, d_io + 2 * B, p.rho0, p.ux0, p.uy0,
                      slot_shift(hdesc[s]), p.nx, p.ny, 0.0, hdesc[s].k0, hdesc[s].k1,
                      (int)(t & 1), y0, rows, st));
     HIPC(hipStreamSynchronize(st));
@@ -496,7 +496,7 @@ int Group::read_moments(int s, int at, double* m) {
   }
   for (int y0 = 0; y0 < p.ny; y0 += band_rows) {
     const int rows = std::min(band_rows, p.ny - y0);
-    HIPC(launch_moments(storage, pop[s], B, d_io, p.nx, p.ny, (int)(t & 1), p.rho0, p.ux0,
+    HIPC(launch_moments(storage, pop[s], hdesc[s].pitch, B, d_io, p.nx, p.ny, (int)(t & 1), p.rho0, p.ux0,
                         p.uy0, slot_shift(hdesc[s]), d_err + s, y0, rows, st));
     const size_t Bn = (size_t)rows * p.nx;
     for (int a = 0; a < 9; ++a)
@@ -570,7 +570,7 @@ int Group::read_fourier_mode(int which, int kx, int ky, double out[2]) {
   if (which < 0 || which > 2) return set_error(FLB_E_ARG, "unknown field %d", which);
   const flb_params& p = P[0];
   const int nkx = ((kx % p.nx) + p.nx) % p.nx, nky = ((ky % p.ny) + p.ny) % p.ny;
-  HIPC(launch_fourier_mode(storage, pop[0], d_mode, kModeBlocks, p.nx, p.ny, (int)(t & 1), which,
+  HIPC(launch_fourier_mode(storage, pop[0], hdesc[0].pitch, d_mode, kModeBlocks, p.nx, p.ny, (int)(t & 1), which,
                            nkx, nky, p.rho0, p.ux0, p.uy0, st));
   std::vector<double2> part(kModeBlocks);
   HIPC(hipMemcpyAsync(part.data(), d_mode, kModeBlocks * sizeof(double2), hipMemcpyDeviceToHost,
@@ -615,7 +615,7 @@ int Group::checkpoint(void* host, size_t bytes) {
   for (int y0 = 0; y0 < p.ny; y0 += band_rows) {
     const int rows = std::min(band_rows, p.ny - y0);
     const size_t B = (size_t)rows * p.nx;
-    HIPC(launch_raw_state(storage, pop[0], d_io, p.nx, p.ny, (int)(t & 1), 1, y0, rows, st));
+    HIPC(launch_raw_state(storage, pop[0], hdesc[0].pitch, d_io, p.nx, p.ny, (int)(t & 1), 1, y0, rows, st));
     for (int i = 0; i < 9; ++i)
       HIPC(hipMemcpyAsync(dst + (i * N + (size_t)y0 * p.nx) * es, (char*)d_io + i * B * es, B * es,
                           hipMemcpyDeviceToHost, st));
@@ -647,7 +647,7 @@ int Group::restore(const void* host, size_t bytes) {
     for (int i = 0; i < 9; ++i)
       HIPC(hipMemcpyAsync((char*)d_io + i * B * es, src + (i * N + (size_t)y0 * p.nx) * es, B * es,
                           hipMemcpyHostToDevice, st));
-    HIPC(launch_raw_state(storage, pop[0], d_io, p.nx, p.ny, (int)(t & 1), 0, y0, rows, st));
+    HIPC(launch_raw_state(storage, pop[0], hdesc[0].pitch, d_io, p.nx, p.ny, (int)(t & 1), 0, y0, rows, st));
     HIPC(hipStreamSynchronize(st));
   }
   return reset_stats();

@@ -13,28 +13,30 @@
 
 namespace flb {
 
-// Element indices of the nine populations a site reads in phase `odd`.
-// After the collision the value of direction kOpp[i] goes back to idx[i].
+// Element indices of the nine populations a site reads in phase `odd`, in
+// the row-interleaved storage (value i of site (x, y) at (9 y + i) P + x,
+// P the row pitch).  After the collision the value of direction kOpp[i]
+// goes back to idx[i].
 __device__ __forceinline__ void site_indices(int x, int y, int nx, int ny, int odd,
-                                             uint32_t N, uint32_t idx[9]) {
+                                             uint32_t P, uint32_t idx[9]) {
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const uint32_t rc = (uint32_t)y * nx, rm = (uint32_t)ym * nx, rp = (uint32_t)yp * nx;
-  const uint32_t c = rc + x;
+  // start of plane row 0 of lattice rows y, y - 1, y + 1
+  const uint32_t rc = 9u * y * P, rm = 9u * ym * P, rp = 9u * yp * P;
   if (!odd) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) idx[i] = (uint32_t)i * N + c;
+    for (int i = 0; i < 9; ++i) idx[i] = rc + (uint32_t)i * P + x;
   } else {
     // plane opp(i) at x - v_i
-    idx[0] = c;
-    idx[1] = 3u * N + rc + xm;   // v=( 1, 0): plane 3 at (x-1, y)
-    idx[2] = 4u * N + rm + x;    // v=( 0, 1): plane 4 at (x, y-1)
-    idx[3] = 1u * N + rc + xp;   // v=(-1, 0): plane 1 at (x+1, y)
-    idx[4] = 2u * N + rp + x;    // v=( 0,-1): plane 2 at (x, y+1)
-    idx[5] = 7u * N + rm + xm;   // v=( 1, 1): plane 7 at (x-1, y-1)
-    idx[6] = 8u * N + rm + xp;   // v=(-1, 1): plane 8 at (x+1, y-1)
-    idx[7] = 5u * N + rp + xp;   // v=(-1,-1): plane 5 at (x+1, y+1)
-    idx[8] = 6u * N + rp + xm;   // v=( 1,-1): plane 6 at (x-1, y+1)
+    idx[0] = rc + x;
+    idx[1] = rc + 3u * P + xm;   // v=( 1, 0): plane 3 at (x-1, y)
+    idx[2] = rm + 4u * P + x;    // v=( 0, 1): plane 4 at (x, y-1)
+    idx[3] = rc + 1u * P + xp;   // v=(-1, 0): plane 1 at (x+1, y)
+    idx[4] = rp + 2u * P + x;    // v=( 0,-1): plane 2 at (x, y+1)
+    idx[5] = rm + 7u * P + xm;   // v=( 1, 1): plane 7 at (x-1, y-1)
+    idx[6] = rm + 8u * P + xp;   // v=(-1, 1): plane 8 at (x+1, y-1)
+    idx[7] = rp + 5u * P + xp;   // v=(-1,-1): plane 5 at (x+1, y+1)
+    idx[8] = rp + 6u * P + xm;   // v=( 1,-1): plane 6 at (x-1, y+1)
   }
 }
 
@@ -42,50 +44,44 @@ __device__ __forceinline__ void site_indices(int x, int y, int nx, int ny, int o
 // Write f (unshifted FP64, natural order, [9][ny][nx]) into storage at phase
 // `odd` (odd: the reversed, un-streamed layout the next odd step reads).
 template <typename S>
-__global__ void write_state_kernel(S* pop, const double* __restrict__ f, int nx, int ny,
-                                   int odd, Shift9 sh, int y0, int rows) {
+__global__ void write_state_kernel(S* pop, uint32_t P, const double* __restrict__ f, int nx,
+                                   int ny, int odd, Shift9 sh, int y0, int rows) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
   if (x >= nx) return;
   const uint32_t B = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
-  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
   uint32_t idx[9];
-  site_indices(x, y, nx, ny, odd, N, idx);
+  site_indices(x, y, nx, ny, odd, P, idx);
 #pragma unroll
   for (int i = 0; i < 9; ++i) pop[idx[i]] = (S)(f[i * (size_t)B + bs] - sh.v[i]);
-  (void)site;
 }
 
 template <typename S>
-__global__ void read_state_kernel(const S* __restrict__ pop, double* f, int nx, int ny, int odd,
-                                  Shift9 sh, int y0, int rows) {
+__global__ void read_state_kernel(const S* __restrict__ pop, uint32_t P, double* f, int nx,
+                                  int ny, int odd, Shift9 sh, int y0, int rows) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
   if (x >= nx) return;
   const uint32_t B = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
-  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
   uint32_t idx[9];
-  site_indices(x, y, nx, ny, odd, N, idx);
+  site_indices(x, y, nx, ny, odd, P, idx);
 #pragma unroll
   for (int i = 0; i < 9; ++i) f[i * (size_t)B + bs] = (double)pop[idx[i]] + sh.v[i];
-  (void)site;
 }
 
 // Raw storage copy in natural (even-phase) order for checkpoints: keeps the
 // stored bits exactly.
 template <typename S>
-__global__ void raw_state_kernel(S* pop, S* buf, int nx, int ny, int odd, int to_buf, int y0,
-                                 int rows) {
+__global__ void raw_state_kernel(S* pop, uint32_t P, S* buf, int nx, int ny, int odd, int to_buf,
+                                 int y0, int rows) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
   if (x >= nx) return;
   const uint32_t B = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
-  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
   uint32_t idx[9];
-  site_indices(x, y, nx, ny, odd, N, idx);
+  site_indices(x, y, nx, ny, odd, P, idx);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     if (to_buf) buf[i * (size_t)B + bs] = pop[idx[i]];
     else pop[idx[i]] = buf[i * (size_t)B + bs];
   }
-  (void)site;
 }
 
 // Equilibrium f^0(rho(x), u(x)) from per-site fields (or uniform values when
@@ -93,7 +89,8 @@ __global__ void raw_state_kernel(S* pop, S* buf, int nx, int ny, int odd, int to
 // sqrt(mu f^0_i) N_i drawn with the thermal tag (two draws per site:
 // step field 0 gives N_0..N_5, step field 1 gives N_6..N_8).
 template <typename S>
-__global__ void init_kernel(S* pop, const double* __restrict__ rho, const double* __restrict__ ux,
+__global__ void init_kernel(S* pop, uint32_t P, const double* __restrict__ rho,
+                            const double* __restrict__ ux,
                             const double* __restrict__ uy, double rho0, double ux0, double uy0,
                             Shift9 sh, int nx, int ny, double mu, uint32_t k0, uint32_t k1,
                             int odd, int y0, int rows) {
@@ -101,7 +98,7 @@ __global__ void init_kernel(S* pop, const double* __restrict__ rho, const double
   if (x >= nx) return;
   const uint32_t bs = (uint32_t)blockIdx.y * nx + x;  // index into band fields
   (void)rows;
-  const uint32_t N = (uint32_t)nx * ny, site = (uint32_t)y * nx + x;
+  const uint32_t site = (uint32_t)y * nx + x;
   const double r = rho ? rho[bs] : rho0;
   const double vx = ux ? ux[bs] : ux0, vy = uy ? uy[bs] : uy0;
   double g[9];
@@ -115,7 +112,7 @@ __global__ void init_kernel(S* pop, const double* __restrict__ rho, const double
     for (int i = 0; i < 3; ++i) n9[6 + i] = b[i];
   }
   uint32_t idx[9];
-  site_indices(x, y, nx, ny, odd, N, idx);
+  site_indices(x, y, nx, ny, odd, P, idx);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double f0 = r * g[i];
@@ -128,15 +125,15 @@ __global__ void init_kernel(S* pop, const double* __restrict__ rho, const double
 // f-norm moments when B is null: M~^0 = rho, M~^1 = M~^2 = 0 (local
 // velocity), M~^{3..8} = L^-1 d.
 template <typename S>
-__global__ void moments_kernel(const S* __restrict__ pop, const double* __restrict__ B,
-                               double* out, int nx, int ny, int odd, double rho0, double ux0,
-                               double uy0, Shift9 sh, int* err, int y0, int rows) {
+__global__ void moments_kernel(const S* __restrict__ pop, uint32_t P,
+                               const double* __restrict__ B, double* out, int nx, int ny, int odd,
+                               double rho0, double ux0, double uy0, Shift9 sh, int* err, int y0,
+                               int rows) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
   if (x >= nx) return;
   const uint32_t Bn = (uint32_t)nx * rows, bs = (uint32_t)blockIdx.y * nx + x;
-  const uint32_t N = (uint32_t)nx * ny;
   uint32_t idx[9];
-  site_indices(x, y, nx, ny, odd, N, idx);
+  site_indices(x, y, nx, ny, odd, P, idx);
   double h[9], f[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -173,9 +170,9 @@ __global__ void moments_kernel(const S* __restrict__ pop, const double* __restri
 
 // Partial sums of one Fourier coefficient sum_x dA(x) e^{-i k.x} per block.
 template <typename S>
-__global__ void fourier_mode_kernel(const S* __restrict__ pop, double2* partial, int nx, int ny,
-                                    int odd, int which, int kx, int ky, double rho0, double ux0,
-                                    double uy0) {
+__global__ void fourier_mode_kernel(const S* __restrict__ pop, uint32_t P, double2* partial,
+                                    int nx, int ny, int odd, int which, int kx, int ky,
+                                    double rho0, double ux0, double uy0) {
   __shared__ double sr[256], si[256];
   const int tid = threadIdx.x;
   const uint32_t N = (uint32_t)nx * ny;
@@ -183,7 +180,7 @@ __global__ void fourier_mode_kernel(const S* __restrict__ pop, double2* partial,
   for (uint32_t site = blockIdx.x * 256u + tid; site < N; site += gridDim.x * 256u) {
     const int y = (int)(site / (uint32_t)nx), x = (int)(site - (uint32_t)y * nx);
     uint32_t idx[9];
-    site_indices(x, y, nx, ny, odd, N, idx);
+    site_indices(x, y, nx, ny, odd, P, idx);
     double h[9];
     for (int i = 0; i < 9; ++i) h[i] = (double)pop[idx[i]];
     const Moments<double> m = hermite_moments(h);
@@ -485,75 +482,79 @@ static dim3 row_grid(int nx, int rows) { return dim3((nx + 255) / 256, rows); }
 
 // The row-parallel utility kernels below process the band of rows
 // [y0, y0 + rows); their host-side arrays hold that band only.
-hipError_t launch_write_state(int storage, void* pop, const double* f, int nx, int ny, int odd,
-                              const Shift9& sh, int y0, int rows, hipStream_t st) {
+hipError_t launch_write_state(int storage, void* pop, uint32_t P, const double* f, int nx, int ny,
+                              int odd, const Shift9& sh, int y0, int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(write_state_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
-                       (double*)pop, f, nx, ny, odd, sh, y0, rows);
+                       (double*)pop, P, f, nx, ny, odd, sh, y0, rows);
   else
     hipLaunchKernelGGL(write_state_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
-                       (float*)pop, f, nx, ny, odd, sh, y0, rows);
+                       (float*)pop, P, f, nx, ny, odd, sh, y0, rows);
   return hipGetLastError();
 }
 
-hipError_t launch_read_state(int storage, const void* pop, double* f, int nx, int ny, int odd,
-                             const Shift9& sh, int y0, int rows, hipStream_t st) {
+hipError_t launch_read_state(int storage, const void* pop, uint32_t P, double* f, int nx, int ny,
+                             int odd, const Shift9& sh, int y0, int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(read_state_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
-                       (const double*)pop, f, nx, ny, odd, sh, y0, rows);
+                       (const double*)pop, P, f, nx, ny, odd, sh, y0, rows);
   else
     hipLaunchKernelGGL(read_state_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
-                       (const float*)pop, f, nx, ny, odd, sh, y0, rows);
+                       (const float*)pop, P, f, nx, ny, odd, sh, y0, rows);
   return hipGetLastError();
 }
 
-hipError_t launch_raw_state(int storage, void* pop, void* buf, int nx, int ny, int odd,
+hipError_t launch_raw_state(int storage, void* pop, uint32_t P, void* buf, int nx, int ny, int odd,
                             int to_buf, int y0, int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(raw_state_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
-                       (double*)pop, (double*)buf, nx, ny, odd, to_buf, y0, rows);
+                       (double*)pop, P, (double*)buf, nx, ny, odd, to_buf, y0, rows);
   else
     hipLaunchKernelGGL(raw_state_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
-                       (float*)pop, (float*)buf, nx, ny, odd, to_buf, y0, rows);
+                       (float*)pop, P, (float*)buf, nx, ny, odd, to_buf, y0, rows);
   return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, void* pop, const double* rho, const double* ux,
+hipError_t launch_init(int storage, void* pop, uint32_t P, const double* rho, const double* ux,
                        const double* uy, double rho0, double ux0, double uy0, const Shift9& sh,
                        int nx, int ny, double mu, uint32_t k0, uint32_t k1, int odd, int y0,
                        int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(init_kernel<double>, row_grid(nx, rows), dim3(256), 0, st, (double*)pop,
-                       rho, ux, uy, rho0, ux0, uy0, sh, nx, ny, mu, k0, k1, odd, y0, rows);
+                       P, rho, ux, uy, rho0, ux0, uy0, sh, nx, ny, mu, k0, k1, odd, y0, rows);
   else
     hipLaunchKernelGGL(init_kernel<float>, row_grid(nx, rows), dim3(256), 0, st, (float*)pop,
-                       rho, ux, uy, rho0, ux0, uy0, sh, nx, ny, mu, k0, k1, odd, y0, rows);
+                       P, rho, ux, uy, rho0, ux0, uy0, sh, nx, ny, mu, k0, k1, odd, y0, rows);
   return hipGetLastError();
 }
 
-hipError_t launch_moments(int storage, const void* pop, const double* B, double* out, int nx,
+hipError_t launch_moments(int storage, const void* pop, uint32_t P, const double* B, double* out,
+                          int nx,
                           int ny, int odd, double rho0, double ux0, double uy0,
                           const Shift9& sh, int* err, int y0, int rows, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(moments_kernel<double>, row_grid(nx, rows), dim3(256), 0, st,
-                       (const double*)pop, B, out, nx, ny, odd, rho0, ux0, uy0, sh, err, y0,
+                       (const double*)pop, P, B, out, nx, ny, odd, rho0, ux0, uy0, sh, err, y0,
                        rows);
   else
     hipLaunchKernelGGL(moments_kernel<float>, row_grid(nx, rows), dim3(256), 0, st,
-                       (const float*)pop, B, out, nx, ny, odd, rho0, ux0, uy0, sh, err, y0,
+                       (const float*)pop, P, B, out, nx, ny, odd, rho0, ux0, uy0, sh, err, y0,
                        rows);
   return hipGetLastError();
 }
 
-hipError_t launch_fourier_mode(int storage, const void* pop, double2* partial, int nblocks,
+hipError_t launch_fourier_mode(int storage, const void* pop, uint32_t P, double2* partial,
+                               int nblocks,
                                int nx, int ny, int odd, int which, int kx, int ky, double rho0,
                                double ux0, double uy0, hipStream_t st) {
   if (storage == 0)
     hipLaunchKernelGGL(fourier_mode_kernel<double>, dim3(nblocks), dim3(256), 0, st,
-                       (const double*)pop, partial, nx, ny, odd, which, kx, ky, rho0, ux0, uy0);
+                       (const double*)pop, P, partial, nx, ny, odd, which, kx, ky, rho0, ux0,
+                       uy0);
   else
     hipLaunchKernelGGL(fourier_mode_kernel<float>, dim3(nblocks), dim3(256), 0, st,
-                       (const float*)pop, partial, nx, ny, odd, which, kx, ky, rho0, ux0, uy0);
+                       (const float*)pop, P, partial, nx, ny, odd, which, kx, ky, rho0, ux0,
+                       uy0);
   return hipGetLastError();
 }
 
@@ -577,27 +578,17 @@ hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st) {
 }
 
 // ------------------------------------------------- bandwidth probe
-// A copy with the step kernel's memory shape and none of its arithmetic:
-// every thread moves one 4-byte element of each of nplanes planes (reads
-// of all planes first, then the writes), coalesced, one element per lane.
-__global__ void planes_copy_kernel(const float* __restrict__ in, float* __restrict__ out,
-                                   uint32_t n, int nplanes) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float v[32];
-#pragma unroll
-  for (int p = 0; p < 32; ++p)
-    if (p < nplanes) v[p] = in[(size_t)p * n + i];
-#pragma unroll
-  for (int p = 0; p < 32; ++p)
-    if (p < nplanes) out[(size_t)p * n + i] = v[p];
+// A plain copy between two contiguous buffers, 16 bytes per lane: the
+// device's streaming ceiling, independent of the populations' layout.
+__global__ void stream_copy_kernel(const float4* __restrict__ in, float4* __restrict__ out,
+                                   size_t n4) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n4) out[i] = in[i];
 }
 
-hipError_t launch_planes_copy(const float* in, float* out, uint32_t n, int nplanes,
-                              hipStream_t st) {
-  if (nplanes < 1 || nplanes > 32) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(planes_copy_kernel, dim3((n + 255) / 256), dim3(256), 0, st, in, out, n,
-                     nplanes);
+hipError_t launch_stream_copy(const void* in, void* out, size_t n4, hipStream_t st) {
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st,
+                     (const float4*)in, (float4*)out, n4);
   return hipGetLastError();
 }
 

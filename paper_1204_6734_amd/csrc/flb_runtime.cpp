@@ -118,8 +118,10 @@ static bool valid_velocity(double ux, double uy) {
 int check_params(const flb_params* p) {
   if (!p) return set_error(FLB_E_ARG, "null parameters");
   if (p->nx < 3 || p->ny < 3) return set_error(FLB_E_ARG, "nx, ny must be >= 3");
-  if ((uint64_t)p->nx * (uint64_t)p->ny * 9ull >= (1ull << 32))
-    return set_error(FLB_E_ARG, "lattice too large (9 nx ny must fit 32 bits)");
+  if ((uint64_t)p->nx + kTileX >= (1ull << 31) ||
+      (uint64_t)row_pitch(p->nx) * (uint64_t)p->ny * 9ull >= (1ull << 32))
+    return set_error(FLB_E_ARG, "lattice too large (9 ny nx, nx rounded up to 64, must fit "
+                                "32 bits)");
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return set_error(FLB_E_ARG, "rho0 must be > 0");
   if (!(p->kT >= 0) || !std::isfinite(p->kT)) return set_error(FLB_E_ARG, "kT must be >= 0");
   for (int a = 0; a < 6; ++a)
@@ -146,11 +148,29 @@ int compute_precision(const flb_params* p) {
   return u > kFp32BasisMaxSpeed ? 0 : 1;
 }
 
+// Elements per plane row of the row-interleaved population storage: nx
+// rounded up to whole wavefronts, so every plane row starts 256-byte
+// aligned (FP32) and a wavefront's loads never straddle two plane rows.
+uint32_t row_pitch(int nx) { return (uint32_t)((nx + kTileX - 1) / kTileX * kTileX); }
+
+// Elements of a lattice's population storage (nine plane rows per row).
+size_t population_elems(int nx, int ny) { return (size_t)9 * ny * row_pitch(nx); }
+
+// Tile shape and count: 256 x 1 tiles (four wavefronts along a row) on rows
+// of at least kWideTileMinNx sites, whose wavefronts then read longer
+// stretches of one row (measured faster), else 64 x 4.
+void tile_shape(int nx, int ny, int* wide, int* tiles_x, int* ntiles) {
+  *wide = nx >= kWideTileMinNx ? 1 : 0;
+  const int tw = *wide ? kTileX * kTileY : kTileX, th = *wide ? 1 : kTileY;
+  *tiles_x = (nx + tw - 1) / tw;
+  *ntiles = *tiles_x * ((ny + th - 1) / th);
+}
+
 void fill_slot(const flb_params* p, SlotDesc* d) {
   d->nx = p->nx;
   d->ny = p->ny;
-  d->tiles_x = (p->nx + kTileX - 1) / kTileX;
-  d->ntiles = d->tiles_x * ((p->ny + kTileY - 1) / kTileY);
+  d->pitch = row_pitch(p->nx);
+  tile_shape(p->nx, p->ny, &d->wide, &d->tiles_x, &d->ntiles);
   // t / tiles_x as a multiply-shift (Granlund-Montgomery, round-up
   // variant): m = ceil(2^k / d) with k = 32 + floor(log2 d) (31 + log2 d for
   // a power of two, where the division is exact) fits 32 bits, and its error
@@ -316,43 +336,90 @@ int finish_covariance(const Stats& S, const std::vector<double>& rec, const doub
 
 extern "C" const char* flb_last_error(void) { return flb::g_err.c_str(); }
 
-extern "C" int flb_copy_probe(int32_t nplanes, uint64_t plane_elems, int32_t reps,
-                              double* ms_per_copy) {
+namespace {
+// Device time of `reps` runs of fn() after three unmeasured ones, on the
+// null stream.
+template <typename Fn>
+hipError_t time_reps(int reps, Fn fn, float* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int w = 0; w < 3 && e == hipSuccess; ++w) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(e0, 0);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(e1, 0);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e;
+}
+}  // namespace
+
+extern "C" int flb_copy_probe(int32_t nx, int32_t ny, int32_t precision, int32_t reps,
+                              double* ms_per_pass) {
   using flb::set_error;
-  if (nplanes < 1 || nplanes > 32 || plane_elems == 0 || plane_elems >= (1ull << 32) ||
-      (uint64_t)nplanes * plane_elems >= (1ull << 40) || reps < 1 || reps > 1000 ||
-      !ms_per_copy)
+  flb_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.nx = nx;
+  p.ny = ny;
+  p.rho0 = 1.0;
+  for (int a = 0; a < 6; ++a) p.tau[a] = 1.0;
+  p.precision = precision;
+  if (reps < 1 || reps > 1000 || !ms_per_pass)
     return set_error(FLB_E_ARG, "copy probe: bad arguments");
-  const size_t bytes = (size_t)nplanes * plane_elems * sizeof(float);
-  float *a = nullptr, *b = nullptr;
-  if (hipMalloc((void**)&a, bytes) != hipSuccess) return set_error(FLB_E_OOM, "copy probe");
-  if (hipMalloc((void**)&b, bytes) != hipSuccess) {
+  const int rc = flb::check_params(&p);
+  if (rc != FLB_OK) return rc;
+  const int storage = precision == FLB_FP64 ? 0 : 1;
+  const size_t bytes = flb::population_elems(nx, ny) * (storage == 0 ? 8 : 4);
+  int wide = 0, tiles_x = 0, ntiles = 0;
+  flb::tile_shape(nx, ny, &wide, &tiles_x, &ntiles);
+  const uint32_t pitch = flb::row_pitch(nx);
+  void* a = nullptr;
+  if (hipMalloc(&a, bytes) != hipSuccess) return set_error(FLB_E_OOM, "copy probe");
+  struct Free {
+    void* a;
+    ~Free() { (void)hipFree(a); }
+  } fr{a};
+  hipError_t e = hipMemset(a, 0, bytes);
+  float ms = 0.f;
+  // one even and one odd pass per repetition
+  if (e == hipSuccess)
+    e = time_reps(reps, [&]() {
+      hipError_t r = flb::launch_stream_probe(storage, a, nx, ny, pitch, wide, tiles_x, ntiles, 0,
+                                              0);
+      if (r == hipSuccess)
+        r = flb::launch_stream_probe(storage, a, nx, ny, pitch, wide, tiles_x, ntiles, 1, 0);
+      return r;
+    }, &ms);
+  if (e != hipSuccess) return flb::hip_fail(e, "copy probe");
+  *ms_per_pass = ms / (2.0 * reps);
+  return FLB_OK;
+}
+
+extern "C" int flb_stream_copy_probe(uint64_t bytes, int32_t reps, double* ms_per_copy) {
+  using flb::set_error;
+  if (bytes == 0 || bytes % 16 != 0 || bytes >= (1ull << 40) || reps < 1 || reps > 1000 ||
+      !ms_per_copy)
+    return set_error(FLB_E_ARG, "stream copy probe: bad arguments");
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, bytes) != hipSuccess) return set_error(FLB_E_OOM, "stream copy probe");
+  if (hipMalloc(&b, bytes) != hipSuccess) {
     (void)hipFree(a);
-    return set_error(FLB_E_OOM, "copy probe");
+    return set_error(FLB_E_OOM, "stream copy probe");
   }
   struct Free {
-    float *a, *b;
+    void *a, *b;
     ~Free() {
       (void)hipFree(a);
       (void)hipFree(b);
     }
   } fr{a, b};
-  hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMemset(a, 0, bytes);
-  if (e == hipSuccess) e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
-  const uint32_t n = (uint32_t)plane_elems;
-  for (int w = 0; w < 3 && e == hipSuccess; ++w) e = flb::launch_planes_copy(a, b, n, nplanes, 0);
-  if (e == hipSuccess) e = hipEventRecord(e0, 0);
-  for (int r = 0; r < reps && e == hipSuccess; ++r)
-    e = flb::launch_planes_copy(a, b, n, nplanes, 0);
-  if (e == hipSuccess) e = hipEventRecord(e1, 0);
-  if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  if (e != hipSuccess) return flb::hip_fail(e, "copy probe");
+  if (e == hipSuccess)
+    e = time_reps(reps, [&]() { return flb::launch_stream_copy(a, b, bytes / 16, 0); }, &ms);
+  if (e != hipSuccess) return flb::hip_fail(e, "stream copy probe");
   *ms_per_copy = ms / reps;
   return FLB_OK;
 }

@@ -17,10 +17,14 @@ namespace flb {
 // validity region).
 constexpr double kFp32BasisMaxSpeed = 0.25;
 
+
 int set_error(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int check_params(const flb_params* p);
 int compute_precision(const flb_params* p);
+uint32_t row_pitch(int nx);
+size_t population_elems(int nx, int ny);
+void tile_shape(int nx, int ny, int* wide, int* tiles_x, int* ntiles);
 void fill_slot(const flb_params* p, SlotDesc* d);
 Shift9 slot_shift(const SlotDesc& d);
 void hermite_rows(double m[81]);
@@ -46,28 +50,30 @@ hipError_t launch_step(int storage, int compute, int basis, bool sample, int odd
                        int total_tiles, const uint64_t* d_clock, uint32_t step_idx,
                        LaunchCfg cfg, hipStream_t st);
 hipError_t launch_tick(uint64_t* d_clock, uint64_t n, hipStream_t st);
-hipError_t launch_write_state(int storage, void* pop, const double* f, int nx, int ny, int odd,
-                              const Shift9& sh, int y0, int rows, hipStream_t st);
-hipError_t launch_read_state(int storage, const void* pop, double* f, int nx, int ny, int odd,
-                             const Shift9& sh, int y0, int rows, hipStream_t st);
-hipError_t launch_raw_state(int storage, void* pop, void* buf, int nx, int ny, int odd,
+hipError_t launch_write_state(int storage, void* pop, uint32_t P, const double* f, int nx, int ny,
+                              int odd, const Shift9& sh, int y0, int rows, hipStream_t st);
+hipError_t launch_read_state(int storage, const void* pop, uint32_t P, double* f, int nx, int ny,
+                             int odd, const Shift9& sh, int y0, int rows, hipStream_t st);
+hipError_t launch_raw_state(int storage, void* pop, uint32_t P, void* buf, int nx, int ny, int odd,
                             int to_buf, int y0, int rows, hipStream_t st);
-hipError_t launch_init(int storage, void* pop, const double* rho, const double* ux,
+hipError_t launch_init(int storage, void* pop, uint32_t P, const double* rho, const double* ux,
                        const double* uy, double rho0, double ux0, double uy0, const Shift9& sh,
                        int nx, int ny, double mu, uint32_t k0, uint32_t k1, int odd, int y0,
                        int rows, hipStream_t st);
-hipError_t launch_moments(int storage, const void* pop, const double* B, double* out, int nx,
-                          int ny, int odd, double rho0, double ux0, double uy0,
+hipError_t launch_moments(int storage, const void* pop, uint32_t P, const double* B, double* out,
+                          int nx, int ny, int odd, double rho0, double ux0, double uy0,
                           const Shift9& sh, int* err, int y0, int rows, hipStream_t st);
-hipError_t launch_fourier_mode(int storage, const void* pop, double2* partial, int nblocks,
+hipError_t launch_fourier_mode(int storage, const void* pop, uint32_t P, double2* partial,
+                               int nblocks,
                                int nx, int ny, int odd, int which, int kx, int ky, double rho0,
                                double ux0, double uy0, hipStream_t st);
 hipError_t launch_close_block(double* partials, int ntiles, double* record, hipStream_t st);
 hipError_t launch_merge_blocks(double* rec, int nhalf, hipStream_t st);
 hipError_t launch_open_sum(const double* partials, int ntiles, double* out, hipStream_t st);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
-hipError_t launch_planes_copy(const float* in, float* out, uint32_t n, int nplanes,
-                              hipStream_t st);
+hipError_t launch_stream_copy(const void* in, void* out, size_t n4, hipStream_t st);
+hipError_t launch_stream_probe(int storage, void* pop, int nx, int ny, uint32_t pitch, int wide,
+                               int tiles_x, int ntiles, int odd, hipStream_t st);
 hipError_t sk_prepare(size_t max_lds);
 hipError_t launch_sk_sample(int storage, void* z, void* zt, double* acc, int nx, int ny,
                             const void* twx, const void* twy, size_t max_lds, hipStream_t st);

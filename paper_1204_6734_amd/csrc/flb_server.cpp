@@ -97,9 +97,9 @@ struct Active {
 };
 
 static size_t request_bytes_of(const flb_params& p, int storage) {
-  const size_t N = (size_t)p.nx * p.ny;
-  const int ntiles = ((p.nx + kTileX - 1) / kTileX) * ((p.ny + kTileY - 1) / kTileY);
-  size_t b = 9 * N * (storage == 0 ? 8 : 4);
+  int wide = 0, tiles_x = 0, ntiles = 0;
+  tile_shape(p.nx, p.ny, &wide, &tiles_x, &ntiles);
+  size_t b = population_elems(p.nx, p.ny) * (storage == 0 ? 8 : 4);
   b = (b + 255) & ~(size_t)255;
   if (p.sample_every > 0) {
     b += ((size_t)ntiles * kNStat * 8 + 255) & ~(size_t)255;
@@ -170,14 +170,13 @@ int flb_server::admit_locked() {
     fill_slot(&a.p, &a.desc);
     a.cls = compute_precision(&a.p);
     char* base = arena + off;
-    const size_t N = (size_t)a.p.nx * a.p.ny;
     size_t o = 0;
     auto take = [&](size_t n) {
       char* p = base + o;
       o += (n + 255) & ~(size_t)255;
       return p;
     };
-    a.desc.pop = take(9 * N * (cfg.precision == 0 ? 8 : 4));
+    a.desc.pop = take(population_elems(a.p.nx, a.p.ny) * (cfg.precision == 0 ? 8 : 4));
     if (a.p.sample_every > 0) {
       a.desc.partials = (double*)take((size_t)a.desc.ntiles * kNStat * 8);
       a.stats.max_blocks = kServerBlocks;
@@ -192,8 +191,8 @@ int flb_server::admit_locked() {
     a.stats.reset(a.p.block_steps);
     // state: equilibrium (or thermal) start, cleared sums and flags
     const double mu = a.p.init == FLB_INIT_THERMAL ? 3.0 * a.p.kT : 0.0;
-    hipError_t e = launch_init(cfg.precision == 0 ? 0 : 1, a.desc.pop, nullptr, nullptr, nullptr,
-                               a.p.rho0, a.p.ux0, a.p.uy0, slot_shift(a.desc), a.p.nx, a.p.ny,
+    hipError_t e = launch_init(cfg.precision == 0 ? 0 : 1, a.desc.pop, a.desc.pitch, nullptr,
+                               nullptr, nullptr, a.p.rho0, a.p.ux0, a.p.uy0, slot_shift(a.desc), a.p.nx, a.p.ny,
                                mu, a.desc.k0, a.desc.k1, 0, 0, a.p.ny, st);
     if (e == hipSuccess && a.desc.partials) {
       e = launch_fill(a.desc.partials, (size_t)a.desc.ntiles * kNStat, 0.0, st);
@@ -213,8 +212,7 @@ int flb_server::admit_locked() {
 
 static double* records_of(const Active& a, char* arena, int precision) {
   if (a.p.sample_every <= 0) return nullptr;
-  const size_t N = (size_t)a.p.nx * a.p.ny;
-  size_t o = (9 * N * (precision == 0 ? 8 : 4) + 255) & ~(size_t)255;
+  size_t o = (population_elems(a.p.nx, a.p.ny) * (precision == 0 ? 8 : 4) + 255) & ~(size_t)255;
   o += ((size_t)a.desc.ntiles * kNStat * 8 + 255) & ~(size_t)255;
   return (double*)(arena + a.off + o);
 }

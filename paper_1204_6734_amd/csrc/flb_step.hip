@@ -6,15 +6,17 @@
 // ("slots"), with the correlator sums of eqs. (16)/(23) and the
 // structure-factor fields of eqs. (24)-(26) fused in when a sample is due.
 //
-// Memory layout: one population array per lattice, structure of arrays
-// [9][ny][nx] of shifted values h_i = f_i - f_i^0(rho0, u0) (FP32 or FP64), updated
+// Memory layout: one population array per lattice of shifted values
+// h_i = f_i - f_i^0(rho0, u0) (FP32 or FP64), row-interleaved (the nine plane
+// rows of each lattice row together, see SlotDesc), updated
 // in place with the two-phase "AA" access pattern: on even steps a site
 // reads its own nine slots and writes the post-collision values back
 // reversed; on odd steps it reads the reversed values of its neighbours and
 // writes forward to its neighbours.  Each site touches the same nine
 // locations it reads, so no second buffer is needed.  The unit of work is a
-// 64 x 4 tile (256 threads, one wavefront per tile row: every wavefront reads
-// and writes whole rows).  A workgroup takes 1, 2 or 4 consecutive tiles
+// tile of 256 sites, one wavefront per 64 consecutive sites of a row: 256 x 1
+// (four wavefronts along a row) on rows of 256 sites or more, else 64 x 4
+// (four rows).  A workgroup takes 1, 2 or 4 consecutive tiles
 // ("tile group"), and the grid is either one workgroup per tile group or a
 // smaller persistent grid striding over the tile groups; the autotuner picks
 // among these shapes, which all compute bit-identical results.  Tile groups
@@ -160,29 +162,32 @@ __device__ __forceinline__ void sample_correlators(const R h[9], bool active, bo
   __syncthreads();  // xs is reused by the next tile
 }
 
-// Byte offsets (within their planes) of the nine populations a site reads
-// in phase ODD, split into a per-lane column part (voff) and a wave-uniform
-// row part (soff, passed in the buffer instruction's scalar offset, so no
-// per-lane add is needed).  Even phase: plane i at the site itself.  Odd
+// Where the nine populations a site reads in phase ODD are, in the
+// row-interleaved storage: the row (a buffer resource of one lattice row,
+// wave-uniform), the plane (the scalar offset, wave-uniform) and the column
+// (the per-lane offset).  Even phase: plane i at the site itself.  Odd
 // phase: plane opp(i) at x - v_i.  After the collision the value of
-// direction kOpp[i] goes back to the same place.  Rows are wave-uniform
-// (one wavefront = 64 sites of one row), so only the x wrap is per lane, and
-// only wavefronts at the two ends of a row can wrap.
+// direction kOpp[i] goes back to the same place.  A wavefront holds 64
+// sites of one row, so only the x wrap is per lane, and only wavefronts at
+// the two ends of a row can wrap.
 template <typename S, int ODD>
-__device__ __forceinline__ void site_offsets(int x, int y, int nx, int ny, bool x_edge,
+__device__ __forceinline__ void site_offsets(void* pop, uint32_t pitch, int x, int y, int nx,
+                                             int ny, bool x_edge, __amdgpu_buffer_rsrc_t rs[9],
                                              uint32_t voff[9], uint32_t soff[9]) {
   constexpr uint32_t E = sizeof(S);
-  const uint32_t rc = (uint32_t)y * nx * E;
+  const uint32_t pe = pitch * E;  // bytes per plane row
   const uint32_t xc = (uint32_t)x * E;
+  const __amdgpu_buffer_rsrc_t rc = row_rsrc<S>(pop, pitch, y);
   if (!ODD) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
+      rs[i] = rc;
       voff[i] = xc;
-      soff[i] = rc;
+      soff[i] = (uint32_t)i * pe;
     }
   } else {
-    const uint32_t rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx * E;
-    const uint32_t rp = (uint32_t)(y == ny - 1 ? 0 : y + 1) * nx * E;
+    const __amdgpu_buffer_rsrc_t rm = row_rsrc<S>(pop, pitch, y == 0 ? ny - 1 : y - 1);
+    const __amdgpu_buffer_rsrc_t rp = row_rsrc<S>(pop, pitch, y == ny - 1 ? 0 : y + 1);
     uint32_t xm = xc - E, xp = xc + E;
     if (x_edge) {
       // a wave-uniform branch: the empty volatile asm keeps the compiler
@@ -191,15 +196,17 @@ __device__ __forceinline__ void site_offsets(int x, int y, int nx, int ny, bool 
       xm = x == 0 ? (uint32_t)(nx - 1) * E : xm;
       xp = x == nx - 1 ? 0u : xp;
     }
-    voff[0] = xc; soff[0] = rc;
-    voff[1] = xm; soff[1] = rc;  // v=( 1, 0) from (x-1, y)
-    voff[2] = xc; soff[2] = rm;  // v=( 0, 1) from (x, y-1)
-    voff[3] = xp; soff[3] = rc;  // v=(-1, 0) from (x+1, y)
-    voff[4] = xc; soff[4] = rp;  // v=( 0,-1) from (x, y+1)
-    voff[5] = xm; soff[5] = rm;  // v=( 1, 1) from (x-1, y-1)
-    voff[6] = xp; soff[6] = rm;  // v=(-1, 1) from (x+1, y-1)
-    voff[7] = xp; soff[7] = rp;  // v=(-1,-1) from (x+1, y+1)
-    voff[8] = xm; soff[8] = rp;  // v=( 1,-1) from (x-1, y+1)
+    rs[0] = rc; voff[0] = xc;  // v=( 0, 0)
+    rs[1] = rc; voff[1] = xm;  // v=( 1, 0) from (x-1, y)
+    rs[2] = rm; voff[2] = xc;  // v=( 0, 1) from (x, y-1)
+    rs[3] = rc; voff[3] = xp;  // v=(-1, 0) from (x+1, y)
+    rs[4] = rp; voff[4] = xc;  // v=( 0,-1) from (x, y+1)
+    rs[5] = rm; voff[5] = xm;  // v=( 1, 1) from (x-1, y-1)
+    rs[6] = rm; voff[6] = xp;  // v=(-1, 1) from (x+1, y-1)
+    rs[7] = rp; voff[7] = xp;  // v=(-1,-1) from (x+1, y+1)
+    rs[8] = rp; voff[8] = xm;  // v=( 1,-1) from (x-1, y+1)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) soff[i] = (uint32_t)kOpp[i] * pe;
   }
 }
 
@@ -224,19 +231,22 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   // lt / tiles_x by multiply-shift on the scalar unit
   const int ty = (int)(((uint64_t)(uint32_t)lt * sd.tx_magic) >> sd.tx_shift);
   const int tx = lt - ty * sd.tiles_x;
-  const int x = tx * kTileX + (threadIdx.x & (kTileX - 1));
-  const int y = ty * kTileY + wave;
+  // first column of this wavefront's 64 sites, and its row: a wide tile
+  // lays its four wavefronts along one row, a narrow one stacks them
+  const int xw = sd.wide ? tx * (kTileY * kTileX) + wave * kTileX : tx * kTileX;
+  const int y = sd.wide ? ty : ty * kTileY + wave;
+  const int x = xw + (threadIdx.x & (kTileX - 1));
   const bool active = live && (x < nx) && (y < ny);
   const uint32_t N = (uint32_t)nx * (uint32_t)ny;
 
+  __amdgpu_buffer_rsrc_t rs[9];
   uint32_t voff[9], soff[9];
   R h[9];
   if (active) {
-    site_offsets<S, ODD>(x, y, nx, ny, tx == 0 || tx == sd.tiles_x - 1, voff, soff);
+    site_offsets<S, ODD>(sd.pop, sd.pitch, x, y, nx, ny, xw == 0 || xw + kTileX >= nx, rs, voff,
+                         soff);
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-      h[i] = (R)buf_load(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), voff[i], soff[i],
-                         (S*)nullptr);
+    for (int i = 0; i < 9; ++i) h[i] = (R)buf_load(rs[i], voff[i], soff[i], (S*)nullptr);
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) h[i] = R(0);
@@ -276,8 +286,7 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
     atomicMin(sd.err_step, (unsigned long long)t);
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
-    buf_store(plane_rsrc<S>(sd.pop, N, ODD ? kOpp[i] : i), voff[i], soff[i], (S)h[kOpp[i]]);
+  for (int i = 0; i < 9; ++i) buf_store(rs[i], voff[i], soff[i], (S)h[kOpp[i]]);
 }
 
 // Tiles per workgroup a step variant accepts: the sampling variants and the
@@ -322,6 +331,47 @@ __global__ __launch_bounds__((kBlock * max_tiles_per_block<R, SAMPLE>())) void s
 }
 
 __global__ void tick_kernel(uint64_t* clock, uint64_t n) { *clock += n; }
+
+// The step's memory traffic with none of its arithmetic (a bandwidth
+// probe): every site of an nx x ny lattice loads its nine values at phase
+// ODD and stores them back as the step does, with the step's tiles,
+// workgroup order and addressing.
+template <typename S, int ODD>
+__global__ __launch_bounds__(kBlock) void stream_probe_kernel(void* pop, int nx, int ny,
+                                                              uint32_t pitch, int wide,
+                                                              int tiles_x, int ntiles) {
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int xw = wide ? tx * (kTileY * kTileX) + wave * kTileX : tx * kTileX;
+  const int y = wide ? ty : ty * kTileY + wave;
+  const int x = xw + (threadIdx.x & (kTileX - 1));
+  if (x >= nx || y >= ny) return;
+  __amdgpu_buffer_rsrc_t rs[9];
+  uint32_t voff[9], soff[9];
+  site_offsets<S, ODD>(pop, pitch, x, y, nx, ny, xw == 0 || xw + kTileX >= nx, rs, voff, soff);
+  S h[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) h[i] = buf_load(rs[i], voff[i], soff[i], (S*)nullptr);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) buf_store(rs[i], voff[i], soff[i], h[kOpp[i]]);
+}
+
+hipError_t launch_stream_probe(int storage, void* pop, int nx, int ny, uint32_t pitch, int wide,
+                               int tiles_x, int ntiles, int odd, hipStream_t st) {
+  const dim3 g(ntiles), b(kBlock);
+#define FLB_PROBE(S)                                                                           \
+  if (odd)                                                                                     \
+    hipLaunchKernelGGL((stream_probe_kernel<S, 1>), g, b, 0, st, pop, nx, ny, pitch, wide,     \
+                       tiles_x, ntiles);                                                       \
+  else                                                                                         \
+    hipLaunchKernelGGL((stream_probe_kernel<S, 0>), g, b, 0, st, pop, nx, ny, pitch, wide,     \
+                       tiles_x, ntiles)
+  if (storage == 0) FLB_PROBE(double);
+  else FLB_PROBE(float);
+#undef FLB_PROBE
+  return hipGetLastError();
+}
 
 // ------------------------------------------------------------ launchers
 template <typename S, typename R, int BASIS>

@@ -99,7 +99,7 @@ int Group::autotune(int reps, flb_launch_config* results, int max_results, int* 
   std::vector<size_t> bytes(n);
   size_t total = 0;
   for (int s = 0; s < n; ++s) {
-    bytes[s] = (size_t)9 * P[s].nx * P[s].ny * (storage == 0 ? sizeof(double) : sizeof(float));
+    bytes[s] = population_elems(P[s].nx, P[s].ny) * (storage == 0 ? sizeof(double) : sizeof(float));
     total += (bytes[s] + 255) & ~(size_t)255;
   }
   const size_t err_bytes = n * (sizeof(int) + sizeof(unsigned long long));

@@ -98,13 +98,31 @@ def test_d3q19_struct_layouts_and_argument_errors():
     assert lib.flb3_lattice_step(None, 1) == F.E_ARG
 
 
+def test_largest_lattice_bound():
+    """Sizes are checked on the host: 9 ny P < 2^32 elements with P = nx
+    rounded up to 64 (the row pitch of the population storage)."""
+    import paper_1204_6734_amd as F
+    lib = F.load()
+    for prec in (F.FP64, F.FP32_SHIFTED):
+        ok = F.make_params(21824, 21824, precision=prec)
+        bad = F.make_params(21825, 21824, precision=prec)
+        assert lib.flb_lattice_bytes(C.byref(ok)) >= 9 * 21824 * 21824 * (8 if prec == F.FP64
+                                                                             else 4)
+        assert lib.flb_lattice_bytes(C.byref(bad)) == 0
+
+
 def test_copy_probe_argument_errors():
+    """Rejected before any device call (no GPU needed)."""
     import paper_1204_6734_amd as F
     lib = F.load()
     ms = C.c_double()
-    for args in [(0, 1024, 5), (33, 1024, 5), (9, 0, 5), (9, 1 << 32, 5), (9, 1024, 0)]:
-        assert lib.flb_copy_probe(*args, C.byref(ms)) == F.E_ARG
-    assert lib.flb_copy_probe(9, 1024, 5, None) == F.E_ARG
+    for args in [(2, 64, 1, 5), (64, 2, 1, 5), (64, 64, 7, 5), (64, 64, 1, 0), (64, 64, 1, 1001),
+                 (1 << 20, 1 << 20, 1, 5)]:
+        assert lib.flb_copy_probe(*args, C.byref(ms)) == F.E_ARG, args
+    assert lib.flb_copy_probe(64, 64, 1, 5, None) == F.E_ARG
+    for args in [(0, 5), (24, 5), (1 << 40, 5), (1024, 0)]:
+        assert lib.flb_stream_copy_probe(*args, C.byref(ms)) == F.E_ARG, args
+    assert lib.flb_stream_copy_probe(1024, 5, None) == F.E_ARG
 
 
 def test_host_arrays_are_size_checked_before_the_call():

@@ -109,8 +109,20 @@ def test_set_launch_rejects_bad_shapes(flb):
         assert e.value.code == flb.E_ARG
 
 
-def test_copy_probe_measures_a_copy(flb):
-    ms = flb.copy_probe(9, 1 << 20, reps=5)
-    gbps = 2 * 9 * (1 << 20) * 4 / (ms * 1e-3) / 1e9
-    print(f"9-plane copy of 2^20 elements: {ms:.4f} ms, {gbps:.0f} GB/s")
+@pytest.mark.parametrize("nx,ny", [(1024, 1024), (100, 30)])
+def test_copy_probe_measures_the_step_pattern(flb, nx, ny):
+    """The no-arithmetic pass moves the step's bytes in a time of the right
+    order, and leaves nothing behind (its own buffer)."""
+    for prec, es in ((flb.FP32_SHIFTED, 4), (flb.FP64, 8)):
+        ms = flb.copy_probe(nx, ny, prec, reps=5)
+        gbps = 18 * es * nx * ny / (ms * 1e-3) / 1e9
+        print(f"{nx}x{ny} step pattern, {es}-byte values: {ms:.4f} ms, {gbps:.0f} GB/s")
+        assert 0 < ms < 100 and gbps > 10
+
+
+def test_stream_copy_probe_measures_a_copy(flb):
+    n = 256 << 20
+    ms = flb.stream_copy_probe(n, reps=5)
+    gbps = 2 * n / (ms * 1e-3) / 1e9
+    print(f"contiguous copy of {n >> 20} MiB: {ms:.4f} ms, {gbps:.0f} GB/s")
     assert 0 < ms < 100 and gbps > 100

@@ -165,9 +165,10 @@ def test_16384_fp32_sampled_sites_by_rows(flb):
 
 
 def test_largest_fp64_lattice_sampled_sites_by_rows(flb):
-    """The largest square lattice the library accepts (9 nx ny < 2^32):
-    21845^2 FP64, 34 GB of populations in 3.8 GB planes, where the 32-bit
-    byte offsets of the buffer accesses reach 89 % of their range."""
-    n = 21845
-    assert 9 * n * n < 2 ** 32 and 9 * (n + 1) * (n + 1) >= 2 ** 32
-    sampled_sites_by_rows(flb, n, n, flb.FP64, 1e-14, "21845^2 FP64")
+    """The largest square lattice the library accepts (9 ny P < 2^32 with the
+    row pitch P = nx rounded up to 64): 21824^2 FP64, 34 GB of populations,
+    where the 32-bit element indices of the row-band kernels reach 99.8 % of
+    their range."""
+    n = 21824
+    assert 9 * n * n < 2 ** 32 and 9 * (n + 1) * (n + 64) >= 2 ** 32
+    sampled_sites_by_rows(flb, n, n, flb.FP64, 1e-14, "21824^2 FP64")
