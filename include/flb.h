@@ -212,6 +212,46 @@ const char* flb_last_error(void);
 int flb_copy_probe(int32_t nx, int32_t ny, int32_t precision, int32_t reps, double* ms_per_pass);
 int flb_stream_copy_probe(uint64_t bytes, int32_t reps, double* ms_per_copy);
 
+/* ------------------------------------------------- no device allocation
+ * For callers that cannot allocate device memory: code under HIP stream
+ * capture, serving loops that own all their memory, harnesses that forbid
+ * allocation.  flb_step_noalloc is flb_lattice_step on populations the
+ * caller holds: nsteps updates of the lattice p describes, starting at
+ * lattice time t0 (the noise of step t is keyed by t, the streaming phase is
+ * t's parity), with the correlator sums of every sampled step.
+ *   p        sizes, reference state, kT, tau, seed, precision, basis and
+ *            sample_every as for flb_lattice_create; p->init and
+ *            p->block_steps are ignored; p->sk_every must be 0 (FLB_E_ARG).
+ *   pop      device buffer of flb_population_bytes(p) bytes holding the
+ *            populations in the library's storage layout at time t0 (e.g.
+ *            copied from flb_lattice_population_buffer of a lattice at that
+ *            time); updated in place.  Caller-owned.
+ *   sums     device array of 54 doubles (caller-owned; may be NULL when
+ *            p->sample_every == 0): overwritten with the sums over the
+ *            call's sampled (site, step) pairs of df_i (9 values) and of
+ *            df_i df_j for i <= j (45, row-major), df = f - f^0(rho0, u0).
+ *   status   device int32 (caller-owned, may be NULL): set to FLB_OK,
+ *            FLB_E_INVALID_VELOCITY or FLB_E_NONFINITE when the work ends.
+ *   hip_stream  the stream the work is enqueued on (NULL: the null stream).
+ * Asynchronous: returns once the work is enqueued (FLB_E_ARG / FLB_E_HIP on
+ * bad arguments or launch failures).  Allocates nothing: the descriptor,
+ * clock, error flags and per-tile partials live in a file-scope device
+ * array of the library (about 14 MiB per device, held until the process
+ * ends), which limits sampled lattices to FLB_NOALLOC_MAX_TILES tiles of
+ * 256 sites (8.4 million sites); unsampled lattices have no such limit.
+ * Every call on a device uses that device's one array, so calls that
+ * overlap on one GPU (other streams, other threads) race; each call clears
+ * what it uses first. */
+#define FLB_NOALLOC_MAX_TILES 32768
+int flb_step_noalloc(const flb_params* p, void* pop, uint64_t t0, uint64_t nsteps, double* sums,
+                     int32_t* status, void* hip_stream);
+/* Bytes of a lattice's population storage (0 for invalid parameters). */
+size_t flb_population_bytes(const flb_params* p);
+/* The device address and size of a lattice's population storage and its
+ * time (the storage's phase): read-only access for copying a state into a
+ * caller's buffer.  Synchronises the lattice's stream. */
+int flb_lattice_population_buffer(flb_lattice* L, void** dev, size_t* bytes, uint64_t* t);
+
 /* ------------------------------------------------------------- ensembles
  * n replicas of one lattice shape (same nx, ny, precision, basis), each with
  * its own rho0, u0, kT, tau, seed and sampling, advanced by one batched

@@ -146,6 +146,10 @@ _SIGS = {
     "flb3_lattice_kernel_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
     "flb_copy_probe": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)],
     "flb_stream_copy_probe": [C.c_uint64, C.c_int32, C.POINTER(C.c_double)],
+    "flb_step_noalloc": [C.POINTER(Params), C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
+                         C.c_void_p, C.c_void_p],
+    "flb_lattice_population_buffer": [C.c_void_p, C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_size_t), C.POINTER(C.c_uint64)],
     "flb_server_create": [C.POINTER(ServerConfig), C.c_void_p, C.POINTER(C.c_void_p)],
     "flb_server_submit": [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)],
     "flb_server_pump": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
@@ -185,6 +189,8 @@ def load(path: str | None = None):
     lib.flb_last_error.restype = C.c_char_p
     lib.flb_lattice_bytes.argtypes = [C.POINTER(Params)]
     lib.flb_lattice_bytes.restype = C.c_size_t
+    lib.flb_population_bytes.argtypes = [C.POINTER(Params)]
+    lib.flb_population_bytes.restype = C.c_size_t
     lib.flb_lattice_checkpoint_bytes.argtypes = [C.c_void_p]
     lib.flb_lattice_checkpoint_bytes.restype = C.c_size_t
     lib.flb_server_request_bytes.argtypes = [C.POINTER(Request)]
@@ -297,6 +303,14 @@ class Lattice(_Tunable):
     @staticmethod
     def bytes_needed(p: Params) -> int:
         return int(load().flb_lattice_bytes(C.byref(p)))
+
+    def population_buffer(self):
+        """(device address, bytes, time) of the lattice's population storage
+        (flb_lattice_population_buffer)."""
+        ptr, nbytes, t = C.c_void_p(), C.c_size_t(), C.c_uint64()
+        _check(load().flb_lattice_population_buffer(self.h, C.byref(ptr), C.byref(nbytes),
+                                                    C.byref(t)), "population_buffer")
+        return int(ptr.value or 0), int(nbytes.value), int(t.value)
 
     def close(self):
         if getattr(self, "h", None):
@@ -444,6 +458,22 @@ class Ensemble(_Tunable):
         n = C.c_uint64()
         _check(load().flb_ensemble_kernel_time(self.h, C.byref(ms), C.byref(n)), "kernel_time")
         return ms.value, n.value
+
+
+def population_bytes(p: Params) -> int:
+    """Bytes of a lattice's population storage (flb_population_bytes)."""
+    return int(load().flb_population_bytes(C.byref(p)))
+
+
+def step_noalloc(p: Params, pop_ptr: int, t0: int, nsteps: int, sums_ptr: int = 0,
+                 status_ptr: int = 0, stream=None):
+    """flb_step_noalloc: nsteps updates of caller-held device populations
+    (pop_ptr) from time t0, the correlator sums into the 54 doubles at
+    sums_ptr and the outcome code into the int32 at status_ptr (device
+    addresses; 0 for none).  Asynchronous on `stream`; allocates nothing."""
+    _check(load().flb_step_noalloc(C.byref(p), C.c_void_p(pop_ptr), t0, nsteps,
+                                   C.c_void_p(sums_ptr or None), C.c_void_p(status_ptr or None),
+                                   _stream_ptr(stream)), "step_noalloc")
 
 
 def copy_probe(nx: int, ny: int, precision: int = FP32_SHIFTED, reps: int = 20) -> float:

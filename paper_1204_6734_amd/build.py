@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libflb.so")
 
-SOURCES = ["flb_step.hip", "flb_kernels.hip", "flb_d3q19.hip", "flb_runtime.cpp",
+SOURCES = ["flb_step.hip", "flb_kernels.hip", "flb_d3q19.hip", "flb_noalloc.hip", "flb_runtime.cpp",
            "flb_group.cpp", "flb_server.cpp", "flb_tune.cpp", "flb_d3q19.cpp"]
 ARCH = os.environ.get("FLB_OFFLOAD_ARCH", "gfx950")
 

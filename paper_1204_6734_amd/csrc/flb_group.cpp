@@ -792,6 +792,17 @@ int flb_lattice_restore(flb_lattice* L, const void* host, size_t bytes) {
   if (!host) return flb::set_error(FLB_E_ARG, "null buffer");
   return L->g.restore(host, bytes);
 }
+int flb_lattice_population_buffer(flb_lattice* L, void** dev, size_t* bytes, uint64_t* t) {
+  NEED(L);
+  if (!dev || !bytes || !t) return flb::set_error(FLB_E_ARG, "null output");
+  const hipError_t e = hipStreamSynchronize(L->g.st);
+  if (e != hipSuccess) return flb::hip_fail(e, "sync");
+  const flb_params& p = L->g.P[0];
+  *dev = L->g.pop[0];
+  *bytes = flb::population_elems(p.nx, p.ny) * (L->g.storage == 0 ? 8 : 4);
+  *t = L->g.t;
+  return FLB_OK;
+}
 uint64_t flb_lattice_time(flb_lattice* L) { return L ? L->g.t : 0; }
 int64_t flb_lattice_error_step(flb_lattice* L) { return L ? L->g.err_step_host : -1; }
 int flb_lattice_profile(flb_lattice* L, int32_t on) {
