@@ -395,7 +395,7 @@ typedef struct {
 } flb_server_config;
 
 typedef struct {
-  flb_params p;            /* p.precision / p.basis are taken from the config      */
+  flb_params p;            /* p.precision / p.basis are ignored: the config's apply */
   uint64_t nsteps;         /* 1 .. 2^62 - 1 (FLB_E_ARG otherwise)                  */
   uint64_t tag;            /* caller's id, returned with the result                */
 } flb_request;
@@ -411,8 +411,11 @@ typedef struct {
 
 typedef struct flb_server flb_server;
 int flb_server_create(const flb_server_config* cfg, void* hip_stream, flb_server** out);
-/* Device bytes a request occupies while admitted. */
-size_t flb_server_request_bytes(const flb_request* r);
+/* Device bytes a request occupies while admitted to a server with this
+ * configuration (the server stores every request in cfg->precision, whatever
+ * r->p.precision says, and admission charges exactly this); 0 for invalid
+ * parameters or a NULL argument. */
+size_t flb_server_request_bytes(const flb_server_config* cfg, const flb_request* r);
 int flb_server_submit(flb_server* S, const flb_request* r, uint64_t* id);
 /* Non-threaded servers: run up to max_chunks chunks (admit, step, retire). */
 int flb_server_pump(flb_server* S, int32_t max_chunks, int32_t* did_work);

@@ -193,7 +193,7 @@ def load(path: str | None = None):
     lib.flb_population_bytes.restype = C.c_size_t
     lib.flb_lattice_checkpoint_bytes.argtypes = [C.c_void_p]
     lib.flb_lattice_checkpoint_bytes.restype = C.c_size_t
-    lib.flb_server_request_bytes.argtypes = [C.POINTER(Request)]
+    lib.flb_server_request_bytes.argtypes = [C.POINTER(ServerConfig), C.POINTER(Request)]
     lib.flb_server_request_bytes.restype = C.c_size_t
     lib.flb3_lattice_error_step.argtypes = [C.c_void_p]
     lib.flb3_lattice_error_step.restype = C.c_int64
@@ -599,9 +599,14 @@ class Server:
             pass
 
     @staticmethod
-    def request_bytes(p: Params, nsteps: int = 1) -> int:
+    def request_bytes(p: Params, nsteps: int = 1, precision: int = FP32_SHIFTED,
+                      basis: int = BASIS_FNORM_LOCAL) -> int:
+        """Device bytes the request occupies in a server storing `precision`
+        (the request's own precision field is not used)."""
+        cfg = ServerConfig()
+        cfg.precision, cfg.basis = precision, basis
         r = Request(p=p, nsteps=nsteps, tag=0)
-        return int(load().flb_server_request_bytes(C.byref(r)))
+        return int(load().flb_server_request_bytes(C.byref(cfg), C.byref(r)))
 
     def submit(self, p: Params, nsteps: int, tag: int = 0) -> int:
         r = Request(p=p, nsteps=int(nsteps), tag=int(tag))

@@ -348,8 +348,13 @@ int flb_server::pump(int max_chunks, int* did) {
 
 extern "C" {
 
-size_t flb_server_request_bytes(const flb_request* r) {
-  return r ? request_bytes_of(r->p, r->p.precision == FLB_FP64 ? 0 : 1) : 0;
+size_t flb_server_request_bytes(const flb_server_config* cfg, const flb_request* r) {
+  if (!cfg || !r) return 0;
+  flb_params p = r->p;
+  p.precision = cfg->precision;
+  p.basis = cfg->basis;
+  if (flb::check_params(&p) != FLB_OK) return 0;
+  return request_bytes_of(p, cfg->precision == FLB_FP64 ? 0 : 1);
 }
 
 int flb_server_create(const flb_server_config* cfg, void* hip_stream, flb_server** out) {

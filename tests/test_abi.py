@@ -111,6 +111,18 @@ def test_largest_lattice_bound():
         assert lib.flb_lattice_bytes(C.byref(bad)) == 0
 
 
+def test_server_request_bytes_follow_the_server_precision():
+    """A request is stored in the server's precision whatever its own
+    precision field says; the sizing call charges what admission charges."""
+    import paper_1204_6734_amd as F
+    p = F.make_params(512, 512, precision=F.FP64, sample_every=1)
+    b32 = F.Server.request_bytes(p, precision=F.FP32_SHIFTED)
+    b64 = F.Server.request_bytes(p, precision=F.FP64)
+    pops = 9 * 512 * 512
+    assert b32 >= 4 * pops and b64 >= 8 * pops and b64 - b32 == 4 * pops
+    assert F.Server.request_bytes(F.make_params(2, 512)) == 0
+
+
 def test_copy_probe_argument_errors():
     """Rejected before any device call (no GPU needed)."""
     import paper_1204_6734_amd as F

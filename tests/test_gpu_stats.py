@@ -10,7 +10,8 @@
 - FP32-shifted and FP64 storage give the same statistics.
 
 "Within 3 SE": every unique entry within 4.5 SE, at least 90 % within 3 SE
-and the rms z-score below 1.6 (45 correlated entries, SE from ~20 blocks).
+and the rms z-score between 0.5 and 1.6 (45 correlated entries, SE from ~20 blocks; the
+lower bound catches an error bar that is too large).
 """
 import math
 
@@ -29,7 +30,7 @@ def zcheck(got, want, se, what):
     z = ((got - want) / se)[iu]
     zmax, zrms, frac3 = np.abs(z).max(), math.sqrt((z ** 2).mean()), (np.abs(z) < 3).mean()
     print(f"{what}: max|z| {zmax:.2f} rms {zrms:.2f} within3 {frac3:.2f}")
-    assert zmax < 4.5 and zrms < 1.6 and frac3 >= 0.9, (what, zmax, zrms, frac3)
+    assert zmax < 4.5 and 0.5 < zrms < 1.6 and frac3 >= 0.9, (what, zmax, zrms, frac3)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

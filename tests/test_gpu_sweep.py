@@ -51,7 +51,7 @@ def test_sweep_covariances_match_theory(flb, sweeps, name):
     zmax, zrms, f3 = zstats(r["dev"], want, r["se"])
     print(f"{name}: <dM dM> vs theory over 11 velocities: max|z| {zmax:.2f} rms {zrms:.2f} "
           f"within3 {f3:.3f}")
-    assert zmax < 5.0 and zrms < 1.6 and f3 >= 0.95
+    assert zmax < 5.0 and 0.5 < zrms < 1.6 and f3 >= 0.95
     # the same weighted fit of both (the true curves have u^3, u^4 terms, so
     # differently weighted fits of them differ by more than the noise)
     l, q, sl, sq = A.lq_maps(US, r["dev"], r["se"])

@@ -241,6 +241,32 @@ def test_noise_free_equilibrium_is_fixed_point(basis):
         np.testing.assert_allclose(O.collide(p, f0), f0, atol=1e-15)
 
 
+@pytest.mark.parametrize("u", [(0.013, -0.027), (0.111, 0.049), (-0.2345, 0.0041)])
+def test_table_basis_fixed_point_off_grid(u):
+    """Table variant (Sec. IV): the basis is that of the nearest grid velocity
+    u_g, and the equilibrium moments are the exact projection
+    M~^{a,0} = sum_i m~_i^a(u_g) f_i^0(rho, u) at the local velocity, so a
+    local equilibrium at a velocity off the grid is still a fixed point of
+    the noise-free collision, for any relaxation times.  The other candidate
+    reading, M~^{a,0} = rho delta^{a0} (exact only on the grid), moves it by
+    ~1e-4; computed here from the oracle's grid basis, it must fail the
+    same check, so the pin tells the two readings apart."""
+    ux, uy = u
+    tau = [0.7, 0.9, 1.1, 1.3, 0.8, 1.2]
+    p = O.make_params(4, 4, kT=0.0, tau=tau, basis=O.BASIS_FNORM_LUT)
+    rho = 1.3
+    f = O.equilibrium(rho, ux, uy)
+    mt, ug = O.lut_basis(ux, uy)
+    assert np.abs(ug - np.array(u)).max() > 1e-3  # genuinely off the grid
+    np.testing.assert_allclose(O.collide(p, f), f, rtol=0, atol=2e-16 * 9)
+    g = O.equilibrium(1.0, *ug)
+    M = mt @ f
+    wrong = f.copy()
+    for a in range(3, 9):
+        wrong += mt[a] * g * (-(M[a] - (rho if a == 0 else 0.0)) / tau[a - 3])
+    assert np.abs(wrong - f).max() > 1e-5
+
+
 @pytest.mark.parametrize("basis", [O.BASIS_FNORM_LOCAL, O.BASIS_HERMITE])
 def test_equal_tau_reduces_to_bgk(basis):
     """All tau^a = tau: the deterministic update is BGK,
@@ -444,7 +470,7 @@ def test_oracle_statistics_match_closed_form_at_rest():
     L.step(6000)
     c = L.covariance()
     zmax, zrms = _zstats(c["cov_f"], T.ideal_covariance_u0_zero(p), c["se_cov_f"])
-    assert zmax < 4.5 and zrms < 1.6, (zmax, zrms)
+    assert zmax < 4.5 and 0.5 < zrms < 1.6, (zmax, zrms)
 
 
 def test_oracle_statistics_match_theory_in_flow():
@@ -459,7 +485,7 @@ def test_oracle_statistics_match_theory_in_flow():
     c = L.covariance()
     C = T.site_covariance(p)
     zmax, zrms = _zstats(c["cov_f"], C, c["se_cov_f"])
-    assert zmax < 4.5 and zrms < 1.6, (zmax, zrms)
+    assert zmax < 4.5 and 0.5 < zrms < 1.6, (zmax, zrms)
     # the ideal-gas f^0 is NOT reached exactly in flow (Sec. IV, Figs. 12-14)
     f0 = O.equilibrium(1.0, 0.15, 0.0)
     assert np.abs(np.diag(C) / (T.noise_strength(1e-5) * f0) - 1).max() > 0.003
