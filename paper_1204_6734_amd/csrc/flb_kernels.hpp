@@ -35,6 +35,8 @@ struct SlotDesc {
   unsigned long long* err_step;  // first failing step (atomicMin)
   int nx, ny, tiles_x, ntiles;
   uint32_t tx_magic, tx_shift;  // local tile t: row of tiles = (t * tx_magic) >> tx_shift
+  uint32_t se_magic, se_shift;  // the same division by sample_every (when > 0)
+  uint32_t sk_magic, sk_shift;  // and by sk_every (when > 0)
   uint64_t t0;          // own time = t0 + clock (mod 2^64)
   uint64_t tend;        // no update once own time >= tend (tend < 2^63)
   uint32_t k0, k1;      // Philox key = seed
@@ -50,6 +52,19 @@ struct SlotDesc {
   float rho0f, ux0f, uy0f, padf_;  // single-precision copies
   float rtf[6], xcf[6], shiftf[9];
 };
+
+// Whether t is a multiple of m (m >= 1; magic, shift for m from magic_div):
+// a multiply-shift for t < 2^31, the 64-bit remainder beyond.  Wave-uniform
+// times keep this on the scalar unit, where the 64-bit remainder alone is a
+// long instruction sequence.
+__host__ __device__ __forceinline__ bool multiple_of(uint64_t t, uint32_t m, uint32_t magic,
+                                                     uint32_t shift) {
+  if ((t >> 31) == 0) {
+    const uint32_t q = (uint32_t)(((uint64_t)(uint32_t)t * magic) >> shift);
+    return (uint32_t)t == q * m;
+  }
+  return t % m == 0;
+}
 
 }  // namespace flb
 

@@ -166,23 +166,27 @@ void tile_shape(int nx, int ny, int* wide, int* tiles_x, int* ntiles) {
   *ntiles = *tiles_x * ((ny + th - 1) / th);
 }
 
+// Division by d >= 1 as a multiply-shift (Granlund-Montgomery, round-up
+// variant): m = ceil(2^k / d) with k = 32 + floor(log2 d) (31 + log2 d for a
+// power of two, where the division is exact) fits 32 bits, and its error
+// e = m d - 2^k < d keeps floor(t m / 2^k) = floor(t / d) for all t < 2^31.
+void magic_div(uint32_t d, uint32_t* magic, uint32_t* shift) {
+  const uint64_t dv = d;
+  int lg = 0;
+  while ((2ull << lg) <= dv) ++lg;  // floor(log2 d)
+  const int k = (dv & (dv - 1)) == 0 ? 31 + lg : 32 + lg;
+  *magic = (uint32_t)(((1ull << k) + dv - 1) / dv);
+  *shift = (uint32_t)k;
+}
+
 void fill_slot(const flb_params* p, SlotDesc* d) {
   d->nx = p->nx;
   d->ny = p->ny;
   d->pitch = row_pitch(p->nx);
   tile_shape(p->nx, p->ny, &d->wide, &d->tiles_x, &d->ntiles);
-  // t / tiles_x as a multiply-shift (Granlund-Montgomery, round-up
-  // variant): m = ceil(2^k / d) with k = 32 + floor(log2 d) (31 + log2 d for
-  // a power of two, where the division is exact) fits 32 bits, and its error
-  // e = m d - 2^k < d keeps floor(t m / 2^k) = floor(t / d) for all t < 2^31
-  {
-    const uint64_t dv = (uint64_t)d->tiles_x;
-    int lg = 0;
-    while ((2ull << lg) <= dv) ++lg;  // floor(log2 d)
-    const int k = (dv & (dv - 1)) == 0 ? 31 + lg : 32 + lg;
-    d->tx_magic = (uint32_t)(((1ull << k) + dv - 1) / dv);
-    d->tx_shift = (uint32_t)k;
-  }
+  magic_div((uint32_t)d->tiles_x, &d->tx_magic, &d->tx_shift);
+  magic_div(p->sample_every > 0 ? (uint32_t)p->sample_every : 1u, &d->se_magic, &d->se_shift);
+  magic_div(p->sk_every > 0 ? (uint32_t)p->sk_every : 1u, &d->sk_magic, &d->sk_shift);
   d->k0 = (uint32_t)p->seed;
   d->k1 = (uint32_t)(p->seed >> 32);
   d->sample_every = p->sample_every;

@@ -25,6 +25,7 @@ int compute_precision(const flb_params* p);
 uint32_t row_pitch(int nx);
 size_t population_elems(int nx, int ny);
 void tile_shape(int nx, int ny, int* wide, int* tiles_x, int* ntiles);
+void magic_div(uint32_t d, uint32_t* magic, uint32_t* shift);
 void fill_slot(const flb_params* p, SlotDesc* d);
 Shift9 slot_shift(const SlotDesc& d);
 void hermite_rows(double m[81]);

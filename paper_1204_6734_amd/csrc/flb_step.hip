@@ -80,9 +80,6 @@ __device__ __forceinline__ CollideConst<double> collide_const<double>(const Slot
   return C;
 }
 
-// Workgroups of the sampling step variants hold at most two tiles.
-constexpr int kSampleTilesPerBlock = 2;
-
 typedef double double4_v __attribute__((ext_vector_type(4)));
 
 // Position of statistic v in a wavefront's 16 x 16 result X^T X (row-major):
@@ -100,40 +97,119 @@ constexpr StatPos stat_positions() {
 }
 __constant__ StatPos kStatPos = stat_positions();
 
+typedef __bf16 bf16x8_v __attribute__((ext_vector_type(8)));
+typedef float float4_v __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4_v __attribute__((ext_vector_type(4)));
+
+// x = x1 + x2 + x3 exactly, each part a bfloat16 (returned as its 16 bits):
+// x1 keeps the leading 8 significant bits of x (truncated), x2 the leading 8
+// of what remains, x3 the rest, which has at most 8 significant bits left
+// (an FP32 value has 24).  Both subtractions are exact.
+__device__ __forceinline__ void split_bf16x3(float x, uint32_t p[3]) {
+  const uint32_t b1 = __builtin_bit_cast(uint32_t, x) & 0xFFFF0000u;
+  const float r1 = x - __builtin_bit_cast(float, b1);
+  const uint32_t b2 = __builtin_bit_cast(uint32_t, r1) & 0xFFFF0000u;
+  const float r2 = r1 - __builtin_bit_cast(float, b2);
+  p[0] = b1 >> 16;
+  p[1] = b2 >> 16;
+  p[2] = __builtin_bit_cast(uint32_t, r2) >> 16;
+}
+
 // Correlator sums of df_i = f_i - f_i^0(rho0, u0) (= the stored h_i): 9
 // first moments and the 45 products i <= j (row-major), added to this
 // tile's open time-block partials.  For one wavefront (64 sites) these are
 // the entries of X^T X, X the 64 x 10 matrix of the nine df_i and a
-// constant 1 per site: sixteen FP64 matrix instructions (16 x 16 output, four
-// sites per instruction) after the wavefront has staged its values in LDS,
-// where lane l picks column l % 16 of site l / 16 of each group of four.  The
-// instruction leaves output row l / 16 + 4 r, column l % 16 in element r of
-// lane l; the wavefront writes the 16 x 16 result over its staged values.
-// The four wavefronts of the tile then add their results in a fixed order,
-// so a tile's partial does not depend on the workgroup shape.  Every thread
-// of the workgroup calls this (it holds two workgroup barriers); `due` is
-// uniform over one tile and says whether the tile samples at all.  Sites
-// outside the lattice stage zeros.
+// constant 1 per site, a dense contraction over the sites done on the
+// matrix cores; the wavefront stages its values in LDS first.
+//   FP32 storage: every df_i is split exactly into three bfloat16 parts,
+//   x = x1 + x2 + x3, so that x y = sum_{p,q} xp yq with every part product
+//   exact in FP32; eighteen v_mfma_f32_16x16x32_bf16 (the nine part pairs,
+//   32 sites each) accumulate the 16 x 16 result in FP32.  Operand layout:
+//   lane l holds feature l % 16 of sites 8 (l / 16) .. + 7 of a group of 32
+//   (the same registers serve as A and B); result row 4 (l / 16) + r,
+//   column l % 16 in element r.  The products are exact and a wavefront's
+//   sum of 64 sites has the rounding of FP32 additions (a few 1e-8
+//   relative); all later sums are FP64.
+//   FP64 storage: sixteen v_mfma_f64_16x16x4f64 (four sites each) on the
+//   values themselves, lane l taking column l % 16 of site l / 16 of each
+//   group of four; result row l / 16 + 4 r, column l % 16 in element r.
+// The wavefront writes its 16 x 16 result (FP64) over its staged values;
+// at the end of the step the four wavefronts of the tile add their results
+// in a fixed order, so a tile's partial does not depend on the workgroup
+// shape.
+template <typename S>
+constexpr int sample_wave_bytes() {
+  // FP32: 3 parts x 10 values (the nine df_i and the constant) x 64 sites
+  // of 2 bytes; FP64: 64 x 9 values; at least the 16 x 16 FP64 result
+  return sizeof(S) == 4 ? 3 * 10 * kTileX * 2 : kTileX * 9 * 8;
+}
+
+// The staging areas of the workgroup's wavefronts: one per wavefront
+// (dynamic LDS, sized at launch for the workgroup's tiles, so that one-tile
+// workgroups keep their occupancy).
+template <typename S>
+__device__ __forceinline__ double* wave_staging(int sub, int wave) {
+  extern __shared__ __attribute__((aligned(16))) double xs_dyn[];
+  constexpr int kWaveDoubles = sample_wave_bytes<S>() / (int)sizeof(double);
+  return xs_dyn + (sub * kTileY + wave) * kWaveDoubles;
+}
+
+// One wavefront's part: X^T X of its 64 sites into its staging area (no
+// barrier).  Sites outside the lattice hold zeros in h.
 template <typename S, typename R>
-__device__ __forceinline__ void sample_correlators(const R h[9], bool active, bool due,
-                                                   double* __restrict__ partials, int sub,
-                                                   int wave) {
-  // per wavefront: 64 x 9 staged values, then its 16 x 16 FP64 result
-  constexpr int kWaveBytes = kTileX * 9 * (int)sizeof(S);
-  static_assert(kWaveBytes >= 16 * 16 * (int)sizeof(double), "result fits the staging area");
-  __shared__ double xs[kSampleTilesPerBlock][kTileY][kWaveBytes / sizeof(double)];
+__device__ __forceinline__ void wave_correlators(const R h[9], int sub, int wave) {
+  static_assert(sample_wave_bytes<S>() >= 16 * 16 * (int)sizeof(double),
+                "the result fits the staging area");
   const int lane = threadIdx.x & 63;
-  const int v = threadIdx.x & (kBlock - 1);
-  const bool adds = due && v < kNStat;
-  const int pos = adds ? kStatPos.pos[v] : 0;
-  if (due) {
-    S* x = reinterpret_cast<S*>(xs[sub][wave]);
+  const int col = lane & 15, grp = lane >> 4;
+  double* out = wave_staging<S>(sub, wave);
+  if constexpr (sizeof(S) == 4) {
+    // staging [part 3][value 10][site 64] of bfloat16; value 9 is the
+    // constant 1 = 1 + 0 + 0 (bfloat16 one is 0x3F80)
+    unsigned short* xb = reinterpret_cast<unsigned short*>(out);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) x[lane * 9 + i] = active ? (S)h[i] : S(0);
-    // the values come back from other lanes of the same wavefront, whose LDS
-    // accesses complete in program order
+    for (int i = 0; i < 9; ++i) {
+      uint32_t pp[3];
+      split_bf16x3((float)h[i], pp);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) xb[(q * 10 + i) * kTileX + lane] = (unsigned short)pp[q];
+    }
+    xb[9 * kTileX + lane] = 0x3F80;
+    xb[19 * kTileX + lane] = 0;
+    xb[29 * kTileX + lane] = 0;
+    // the values come back from other lanes of the same wavefront, whose
+    // LDS accesses complete in program order
     __builtin_amdgcn_wave_barrier();
-    const int col = lane & 15, grp = lane >> 4;
+    // rows 10..15 of the result are not used: those lanes read row 9
+    const int colr = col < 10 ? col : 9;
+    u32x4_v X[3][2];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh)
+        X[q][hh] = *reinterpret_cast<const u32x4_v*>(xb + (q * 10 + colr) * kTileX + 32 * hh +
+                                                     8 * grp);
+    // the result is written over the staged values: every read above is
+    // issued first (the compiler may not move the writes before them)
+    asm volatile("" ::: "memory");
+    // one accumulator: the eighteen products in a fixed order
+    float4_v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_v, X[p][hh]),
+                                                         __builtin_bit_cast(bf16x8_v, X[q][hh]),
+                                                         acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(4 * grp + r) * 16 + col] = (double)acc[r];
+  } else {
+    S* x = reinterpret_cast<S*>(out);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) x[lane * 9 + i] = (S)h[i];
+    __builtin_amdgcn_wave_barrier();
     // columns 10..15 are zero and column 9 is the constant; every lane reads
     // an in-range element so that the sixteen reads issue back to back
     const int colr = col < 9 ? col : 8;
@@ -141,8 +217,6 @@ __device__ __forceinline__ void sample_correlators(const R h[9], bool active, bo
     S xv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) xv[q] = x[(4 * q + grp) * 9 + colr];
-    // the result is written over the staged values: every read above is
-    // issued first (the compiler may not move the writes before them)
     asm volatile("" ::: "memory");
     double4_v acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -150,16 +224,28 @@ __device__ __forceinline__ void sample_correlators(const R h[9], bool active, bo
       const double val = col < 9 ? (double)xv[q] : pad;
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
     }
-    double* out = xs[sub][wave];
 #pragma unroll
     for (int r = 0; r < 4; ++r) out[(grp + 4 * r) * 16 + col] = acc[r];
   }
+}
+
+// The tile's part: after a workgroup barrier, 54 threads add the four
+// wavefronts' results in a fixed order to the tile's partials.  Every
+// thread of the workgroup calls this; `due` is uniform over one tile.  No
+// second barrier: a sampling step gives every tile of a workgroup its own
+// staging areas and is never persistent, so nothing reuses them.
+template <typename S>
+__device__ __forceinline__ void tile_correlators(bool due, double* __restrict__ partials,
+                                                 int sub) {
+  const int v = threadIdx.x & (kBlock - 1);
+  const bool adds = due && v < kNStat;
+  const int pos = adds ? kStatPos.pos[v] : 0;
   __syncthreads();
   if (adds) {
-    const double tot = (xs[sub][0][pos] + xs[sub][1][pos]) + (xs[sub][2][pos] + xs[sub][3][pos]);
+    const double tot = (wave_staging<S>(sub, 0)[pos] + wave_staging<S>(sub, 1)[pos]) +
+                       (wave_staging<S>(sub, 2)[pos] + wave_staging<S>(sub, 3)[pos]);
     partials[v] += tot;
   }
-  __syncthreads();  // xs is reused by the next tile
 }
 
 // Where the nine populations a site reads in phase ODD are, in the
@@ -252,12 +338,20 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
     for (int i = 0; i < 9; ++i) h[i] = R(0);
   }
 
+  const CollideConst<R> C = collide_const<R>(sd);
+  const uint32_t site = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
+  // the Gaussians need only the site and the step: drawn here, while the
+  // loads are still in flight, they cover part of the load latency
+  R Nu[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  if (active && C.noise) unit_gaussians<R, (sizeof(S) < sizeof(R))>(C, site, t, Nu);
+
+  bool due = false;
   if (SAMPLE) {
-    const bool due = live && sd.sample_every > 0 && t % (uint64_t)sd.sample_every == 0;
-    sample_correlators<S, R>(h, active, due, sd.partials + (size_t)(due ? lt : 0) * kNStat,
-                             sub, wave);
-    if (live && sd.skz != nullptr && sd.sk_every > 0 && t % (uint64_t)sd.sk_every == 0 &&
-        active) {
+    due = live && sd.sample_every > 0 &&
+          multiple_of(t, (uint32_t)sd.sample_every, sd.se_magic, sd.se_shift);
+    if (due) wave_correlators<S, R>(h, sub, wave);
+    if (live && sd.skz != nullptr && sd.sk_every > 0 &&
+        multiple_of(t, (uint32_t)sd.sk_every, sd.sk_magic, sd.sk_shift) && active) {
       // structure-factor fields in the f-norm at (rho0, u0): d rho and
       // dj~ = sqrt3 (j - u0 rho) = sqrt3 ((j - rho0 u0) - u0 (rho - rho0))  (eq. (34)),
       // packed as z1 = d rho + i dj~_x, z2 = dj~_y in the storage precision
@@ -266,27 +360,24 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
 #pragma unroll
       for (int i = 0; i < 9; ++i) hd[i] = (double)h[i];
       const Moments<double> m = hermite_moments(hd);
-      const uint32_t site = (uint32_t)y * nx + x;
       V* z = reinterpret_cast<V*>(sd.skz);
       z[site] = V{(S)m.drho, (S)(1.7320508075688772935 * (m.jx - sd.ux0 * m.drho))};
       z[N + site] = V{(S)(1.7320508075688772935 * (m.jy - sd.uy0 * m.drho)), S(0)};
     }
   }
 
-  if (!active) return;
-  const CollideConst<R> C = collide_const<R>(sd);
-  const uint32_t site = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
-  // the Gaussians need only the site and the step: drawn here, while the
-  // loads are still in flight, they cover part of the load latency
-  R Nu[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-  if (C.noise) unit_gaussians<R, (sizeof(S) < sizeof(R))>(C, site, t, Nu);
-  const int e = collide<R, BASIS>(h, C, Nu);
-  if (e) {
-    atomicOr(sd.err, e);
-    atomicMin(sd.err_step, (unsigned long long)t);
-  }
+  if (active) {
+    const int e = collide<R, BASIS>(h, C, Nu);
+    if (e) {
+      atomicOr(sd.err, e);
+      atomicMin(sd.err_step, (unsigned long long)t);
+    }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) buf_store(rs[i], voff[i], soff[i], (S)h[kOpp[i]]);
+    for (int i = 0; i < 9; ++i) buf_store(rs[i], voff[i], soff[i], (S)h[kOpp[i]]);
+  }
+  // the tile's correlator sums last, so that its barrier does not hold the
+  // wavefronts between their loads and their stores
+  if (SAMPLE) tile_correlators<S>(due, sd.partials + (size_t)(due ? lt : 0) * kNStat, sub);
 }
 
 // Tiles per workgroup a step variant accepts: the sampling variants and the
@@ -296,9 +387,6 @@ template <typename R, bool SAMPLE>
 constexpr int max_tiles_per_block() {
   return (SAMPLE || sizeof(R) == 8) ? 2 : kMaxTilesPerBlock;
 }
-static_assert(max_tiles_per_block<float, true>() <= kSampleTilesPerBlock &&
-                  max_tiles_per_block<double, true>() <= kSampleTilesPerBlock,
-              "the correlator staging holds kSampleTilesPerBlock tiles");
 
 // The batched step: blockDim.x / 256 tiles per workgroup.  Without PERSIST
 // workgroup b takes tile group b; with PERSIST (a grid smaller than the
@@ -389,8 +477,9 @@ static hipError_t launch_step_t(bool sample, int odd, const SlotDesc* d_slots,
   const int grid =
       !sample && cfg.grid_blocks > 0 && cfg.grid_blocks < ngroups ? cfg.grid_blocks : ngroups;
   const dim3 g(grid), b(kBlock * tpb);
-#define FLB_STEP(SMP, ODD, PER)                                                                 \
-  hipLaunchKernelGGL((step_kernel<S, R, BASIS, SMP, ODD, PER>), g, b, 0, st, d_slots, d_prefix, \
+  const size_t lds = sample ? (size_t)tpb * kTileY * sample_wave_bytes<S>() : 0;
+#define FLB_STEP(SMP, ODD, PER)                                                                   \
+  hipLaunchKernelGGL((step_kernel<S, R, BASIS, SMP, ODD, PER>), g, b, lds, st, d_slots, d_prefix, \
                      nslots, total_tiles, d_clock, step_idx)
   if (sample) {
     if (odd) FLB_STEP(true, 1, false);
