@@ -29,6 +29,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -37,6 +39,14 @@ BYTES_PER_SITE = {"f32": 72, "f64": 144}
 # D3Q19 FP32 f-norm step: VALU wavefront instructions per wavefront (= per
 # site), profiles/step3_fp32_256cube_d3q19.md
 D3Q19_VALU_PER_SITE = 2517
+# FP32 floating-point operations per site of that kernel: its FMAs (2 each:
+# 1340 v_fma + 280 v_fmac + 84 v_fmamk) and adds and multiplies (1 each: 309
+# v_mul + 101 v_add + 65 others) in the gfx950 code, 3883 in all
+# (profiles/step3_fp32_256cube_d3q19.md); one lane computes one site.
+D3Q19_FLOPS_PER_SITE = 3883
+# FP32 vector peak without packed (two-wide) instructions, which this
+# library does not use: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9
 # VALU issue peak: 256 CUs x 4 SIMDs, one wavefront instruction (64 lanes,
 # 16 per cycle) every 4 cycles at 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
@@ -72,25 +82,84 @@ def traffic_from_profiles(name: str):
 BASES = {"fnorm": ("fnorm_local", 0), "hermite": ("hermite", 1), "lut": ("fnorm_lut", 2)}
 
 
-def cpu_baseline(seconds: float = 12.0, basis: int = 0, ux0: float = 0.1) -> dict:
-    """FP64 oracle on a bounded sample: a 128 x 128 lattice with the large
-    workload's parameters (and basis), stepped until ~`seconds` of CPU time."""
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(nx: int, ny: int, threads: int, seconds: float = 0.0, steps: int = 0,
+                **kw) -> dict:
+    """MLUPS of the FP64 oracle on an nx x ny lattice with `threads` threads,
+    for `steps` steps or until ~`seconds` have passed (chunks of 20)."""
     import oracle as O
-    from paper_1204_6734_amd import inputs as I
+    O.set_threads(threads)
+    try:
+        L = O.Lattice(O.make_params(nx, ny, **kw))
+        L.step(2)
+        done, t0 = 0, time.perf_counter()
+        while (steps and done < steps) or (not steps and time.perf_counter() - t0 < seconds):
+            k = min(20, steps - done) if steps else 20
+            L.step(k)
+            done += k
+        dt = time.perf_counter() - t0
+        L.close()
+    finally:
+        O.set_threads(1)
+    return {"mlups": nx * ny * done / dt / 1e6, "steps": done, "seconds": round(dt, 2),
+            "threads": threads}
+
+
+def cpu_baseline(seconds: float = 12.0, basis: int = 0, ux0: float = 0.1) -> dict:
+    """FP64 oracle on a bounded sample of the large workload (a 128 x 128
+    lattice with its parameters and basis): a third of ~`seconds` on one
+    thread, the rest on every host core (the oracle's per-site loops in
+    OpenMP threads)."""
     nx = ny = 128
-    p = O.make_params(nx, ny, rho0=1.0, ux0=ux0, kT=1e-4, seed=1, init=O.INIT_FIELDS,
-                      basis=basis)
-    L = O.Lattice(p)
-    L.set_fields(*I.shear_wave_fields(nx, ny, ux0=ux0, amp=1e-3))
-    L.step(5)
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        L.step(20)
-        steps += 20
-    dt = time.perf_counter() - t0
-    return {"value": nx * ny * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{nx}x{ny} lattice, same parameters as the timed workload, {steps} steps, "
-                      f"FP64 C oracle single-threaded, {dt:.1f} s"}
+    kw = dict(rho0=1.0, ux0=ux0, kT=1e-4, seed=1, basis=basis)
+    cores = host_cores()
+    one = oracle_rate(nx, ny, 1, seconds=seconds / 3, **kw)
+    allc = oracle_rate(nx, ny, cores, seconds=2 * seconds / 3, **kw)
+    return {"value": allc["mlups"], "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{nx}x{ny} lattice, same parameters as the timed workload, FP64 C "
+                      f"oracle: {allc['steps']} steps on {cores} threads in "
+                      f"{allc['seconds']} s; {one['steps']} steps on 1 thread in "
+                      f"{one['seconds']} s", "single_thread_mlups": one["mlups"],
+            "cpu_model": cpu_model()}
+
+
+def cpu_plan() -> dict:
+    """The oracle timings of the statistics workloads, one thread and every
+    core: 32 x 32 at rest for 1e4 steps sampling every step, and 1e3 steps
+    of the 256 x 256 mixed-tau workload per u_x0 in {0, 0.1, 0.2}."""
+    from paper_1204_6734_amd import inputs as I
+    cores = host_cores()
+    out = {"cores": cores, "cpu_model": cpu_model()}
+    for threads in (1, cores):
+        r = oracle_rate(32, 32, threads, steps=10000, kT=1e-4, seed=1, sample_every=1,
+                        block_steps=500)
+        out[f"32x32_rest_1e4_steps_{threads}t"] = r
+        print(f"cpu plan: 32x32 on {threads} threads: {r['mlups']:.2f} MLUPS",
+              file=sys.stderr, flush=True)
+        for u in (0.0, 0.1, 0.2):
+            r = oracle_rate(256, 256, threads, steps=1000, ux0=u, kT=1e-4,
+                            tau=I.mixed_taus(2), seed=1, sample_every=1, block_steps=500)
+            out[f"256x256_mixed_tau_u{u:g}_1e3_steps_{threads}t"] = r
+            print(f"cpu plan: 256x256 u0={u} on {threads} threads: {r['mlups']:.2f} MLUPS",
+                  file=sys.stderr, flush=True)
+    return out
 
 
 def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 100,
@@ -129,21 +198,46 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
     torch.cuda.synchronize()
     L.profile(True)
     L.kernel_time()  # reset
+    tw0 = L.t
     t0 = time.perf_counter()
     log = run(steps)
     L.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kms, launches = L.kernel_time()
+    L.profile(False)
     sites = nx * nx
+    # structure-factor samples and mode logs that fell in the timed steps
+    n_sk = (len([t for t in range(tw0, tw0 + steps) if t % every == 0]) if every > 0 else 0)
+    with_sk = None
+    if every > 0:
+        # one window of `every` steps holding exactly one S(k) sample and one
+        # mode readback: the rate of the whole workload at its own ratio
+        ahead = (every - L.t % every) % every
+        if ahead:
+            L.step(ahead)
+        L.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.step(every)  # samples S(k) at its first step
+        L.fourier_mode(2, 1, 0)
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        with_sk = {"steps": every, "sk_samples": 1, "mode_logs": 1,
+                   "ms_per_step": round(dt1 * 1e3 / every, 4),
+                   "mlups": round(sites * every / dt1 / 1e6, 1)}
     return {"sites": sites, "dt": dt, "kernel_ms": kms / max(launches, 1), "launches": launches,
             "mode_log": [abs(z) for z in log[-3:]],
+            "sk_in_window": n_sk, "mode_logs_in_window": len(log), "with_sk": with_sk,
             "launch": {"chosen": L.get_launch(), "candidates": tune},
             "config": {"workload": f"{nx}x{nx} D2Q9 {'FP32-shifted' if fp32 else 'FP64'}, "
                                    f"{'' if basis == 'fnorm' else bname + ' basis, '}"
                                    f"rho0=1, u_x0={ux0:g}, kT=1e-4, "
                                    f"tau=1, shear wave 1e-3 sin(2 pi x/L); " +
-                                   (f"S(k) and j~_y(2 pi/L) every {every} steps" if every > 0
+                                   (f"S(k) and j~_y(2 pi/L) every {every} steps "
+                                    f"({n_sk} S(k) samples and {len(log)} mode logs in the "
+                                    f"{steps} timed steps; 'with_sk' times {every} steps "
+                                    f"holding one of each)" if every > 0
                                     else "no S(k), no mode log") +
                                    (f"; correlators every {sample_every} steps"
                                     if sample_every > 0 else ""),
@@ -272,28 +366,47 @@ def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256):
     sites = n ** 3
     kernel_ms = kms / max(launches, 1)
     achieved = 152 * sites / (kernel_ms * 1e-3) / 1e9
-    # the kernel is bound by VALU issue: wavefront instructions per site from
-    # the SQ_INSTS_VALU / SQ_WAVES counters of the profile summary (one
-    # wavefront instruction serves 64 sites), against the issue peak
+    # the kernel is bound by its vector arithmetic: FP32 flops per site (from
+    # its code) against the unpacked FP32 vector peak; beside it the HBM
+    # fraction of its 152 algorithmic bytes per site, and its VALU issue
+    # (wavefront instructions per site from the SQ_INSTS_VALU counter)
+    tflops = D3Q19_FLOPS_PER_SITE * sites / (kernel_ms * 1e-3) / 1e12
     wave_instr = D3Q19_VALU_PER_SITE * sites / 64
-    issue_ms = wave_instr / VALU_ISSUE_PEAK * 1e3
-    rate = wave_instr / (kernel_ms * 1e-3) / 1e9
     return {"mlups": sites * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps,
             "kernel_ms": kernel_ms, "sites": sites, "steps": steps,
-            "roofline": {"bound": "alu", "achieved": round(rate, 1),
-                         "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
-                         "unit": "G wavefront VALU instructions/s",
-                         "frac": round(rate * 1e9 / VALU_ISSUE_PEAK, 4),
-                         "valu_per_site": D3Q19_VALU_PER_SITE,
-                         "issue_bound_ms": round(issue_ms, 4),
-                         "model": "SQ_INSTS_VALU per wavefront at one wavefront instruction "
-                                  "per 4 cycles per SIMD, 1024 SIMDs, 2.4 GHz; the model "
-                                  "charges every instruction a full VALU slot (transcendentals "
-                                  "issue to their own unit), so frac can exceed 1 (1.00-1.07 "
-                                  "measured): frac near 1 means bound by VALU issue",
+            "roofline": {"bound": "alu", "achieved": round(tflops, 2),
+                         "peak": round(FP32_VECTOR_PEAK / 1e12, 1), "unit": "TFLOP/s",
+                         "frac": round(tflops * 1e12 / FP32_VECTOR_PEAK, 4),
+                         "flops_per_site": D3Q19_FLOPS_PER_SITE,
                          "kernel": "step3_kernel<float,float,fnorm>"},
             "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_site": 152}}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_site": 152},
+            "valu_issue": {"wavefront_instructions_per_site": D3Q19_VALU_PER_SITE,
+                           "issue_ms_at_4_cycles": round(wave_instr / VALU_ISSUE_PEAK * 1e3,
+                                                         4)}}
+
+
+def run_config2(F) -> dict:
+    """The 256 x 256 mixed-relaxation-time statistics workload, FP64 and
+    FP32-shifted, u_x0 in {0, 0.1, 0.2}: rate of the sampled steps (each with
+    the correlator sums, every tenth with a structure-factor sample) and the
+    statistical resolution reached (largest relative standard error of the
+    moment covariances' diagonal)."""
+    from paper_1204_6734_amd import analysis as A
+    out = {}
+    for prec, code in (("fp64", F.FP64), ("fp32", F.FP32_SHIFTED)):
+        for u in (0.0, 0.1, 0.2):
+            r = A.mixed_tau_statistics(F, code, u)
+            c = r["cov"]
+            d = np.diag(c["cov_m_fnorm_u0"])[3:]
+            se = np.diag(c["se_cov_m"])[3:]
+            out[f"{prec}_u{u:g}"] = {
+                "mlups_sampled": round(256 * 256 * r["steps"] / r["seconds"] / 1e6, 1),
+                "seconds_sampled": round(r["seconds"], 3), "nsamples": c["nsamples"],
+                "nblocks": c["nblocks"], "max_rel_se_diag": float((se / d).max())}
+            print(f"config2 {prec} u0={u}: {out[f'{prec}_u{u:g}']}", file=sys.stderr,
+                  flush=True)
+    return out
 
 
 def copy_calibration(reps: int = 5):
@@ -316,7 +429,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "ensemble", "serve", "paper", "d3q19"])
+                    choices=["large", "ensemble", "serve", "paper", "d3q19", "config2",
+                             "cpu"])
     ap.add_argument("--requests", type=int, default=None,
                     help="serving window (default 40 in the main line, 400 with --workload serve)")
     ap.add_argument("--no-serving", action="store_true")
@@ -371,6 +485,17 @@ def main():
                                       "table), mu/rho0 = 1e-6", "seconds": time.perf_counter() - t0,
                           **r}), flush=True)
         return
+    if args.workload == "cpu":
+        print(json.dumps({"workload": "oracle timings of the statistics workloads",
+                          **cpu_plan()}), flush=True)
+        return
+    if args.workload == "config2":
+        r = run_config2(F)
+        print(json.dumps({"workload": "256x256 D2Q9, u_x0 in {0, 0.1, 0.2}, kT=1e-4, six "
+                                      "tau from U[0.6, 1.5], 2e4 + 1e5 steps, correlators "
+                                      "every step, S(k) every 10 steps, FP64 and "
+                                      "FP32-shifted", **r}), flush=True)
+        return
     if args.workload == "serve":
         r = run_serving(F, torch, nreq=args.requests or 400, rate=args.rate)
         print(json.dumps({"workload": f"serving, Poisson {args.rate:g}/s", **r}), flush=True)
@@ -413,6 +538,9 @@ def main():
                                              "16 B per thread"}},
         "pct_hbm_roofline": round(100 * mlups * 1e6 * bps / (HBM_PEAK_GBS * 1e9), 2),
         "launch": r["launch"],
+        "structure_factor": {"sk_every": args.sk_every, "sk_samples_in_window": r["sk_in_window"],
+                             "mode_logs_in_window": r["mode_logs_in_window"],
+                             "with_sk": r["with_sk"]},
     }
     if not args.no_serving:
         out["serving"] = run_serving(F, torch, nreq=args.requests or 40)

@@ -41,8 +41,8 @@ def build(force: bool = False) -> str:
     ):
         tmp = _SO + f".tmp{os.getpid()}"
         subprocess.check_call(
-            ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-fPIC", "-shared",
-             "-o", tmp, _SRC, _SRC3, "-lm"]
+            ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-fopenmp", "-fPIC",
+             "-shared", "-o", tmp, _SRC, _SRC3, "-lm"]
         )
         os.replace(tmp, _SO)
     return _SO
@@ -88,6 +88,7 @@ def lib():
         L.flbref_collide.argtypes = [C.POINTER(Params), d, C.c_uint64, C.c_uint64, d]
         L.flbref_collide_lut_at.argtypes = [C.POINTER(Params), d, C.c_uint64, C.c_uint64,
                                             C.c_int32, C.c_int32, d]
+        L.flbref_set_threads.argtypes = [C.c_int]
         L.flbref_lattice_create.argtypes = [C.POINTER(Params), C.POINTER(C.c_void_p)]
         L.flbref_lattice_set_fields.argtypes = [C.c_void_p, d, d, d]
         L.flbref_lattice_set_populations.argtypes = [C.c_void_p, d, C.c_uint64]
@@ -105,6 +106,12 @@ def lib():
         L.flbref_lattice_error_step.restype = C.c_int64
         L.flbref_lattice_destroy.argtypes = [C.c_void_p]
     return _lib
+
+
+def set_threads(n: int):
+    """Threads of the lattice calls' per-site loops (results do not depend
+    on it)."""
+    lib().flbref_set_threads(int(n))
 
 
 def _dp(a: np.ndarray):

@@ -322,6 +322,14 @@ static int collide_with(const flbref_params* p, const double f[9], uint64_t site
 }
 
 /* ------------------------------------------------------------------ */
+/* Threads for the per-site loops of the lattice calls (1 unless set; the
+ * results do not depend on it: every site and every Fourier coefficient is
+ * computed on its own, and the correlator sums stay serial). */
+static int g_threads = 1;
+
+void flbref_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+
+/* ------------------------------------------------------------------ */
 /* Lattice: periodic nx x ny, populations f[i][y][x] (structure of arrays). */
 #define MAX_TBLOCKS 1024
 
@@ -570,6 +578,7 @@ static void dft2(const flbref_lattice* L, const double* a, double* re, double* i
   const int nx = L->p.nx, ny = L->p.ny;
   double* tr = (double*)malloc(L->n * sizeof(double));
   double* ti = (double*)malloc(L->n * sizeof(double));
+#pragma omp parallel for schedule(static) num_threads(g_threads)
   for (int y = 0; y < ny; ++y)
     for (int kx = 0; kx < nx; ++kx) {
       double sr = 0.0, si = 0.0;
@@ -581,6 +590,7 @@ static void dft2(const flbref_lattice* L, const double* a, double* re, double* i
       tr[(size_t)y * nx + kx] = sr;
       ti[(size_t)y * nx + kx] = si;
     }
+#pragma omp parallel for schedule(static) num_threads(g_threads)
   for (int ky = 0; ky < ny; ++ky)
     for (int kx = 0; kx < nx; ++kx) {
       double sr = 0.0, si = 0.0;
@@ -631,6 +641,12 @@ int flbref_lattice_step(flbref_lattice* L, uint64_t nsteps) {
     const uint64_t t = L->t;
     if (L->p.sample_every > 0 && t % (uint64_t)L->p.sample_every == 0) sample_correlators(L);
     if (L->p.sk_every > 0 && t % (uint64_t)L->p.sk_every == 0) sample_structure_factor(L);
+    /* sites collide independently (rows spread over the threads); a failing
+     * site leaves the populations unchanged and reports the lowest failing
+     * site's error */
+    size_t first_bad = n;
+    int first_rc = FLBREF_OK;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         const size_t s = (size_t)y * nx + x;
@@ -638,11 +654,18 @@ int flbref_lattice_step(flbref_lattice* L, uint64_t nsteps) {
         for (int i = 0; i < 9; ++i) f[i] = L->f[i * n + s];
         const int rc = flbref_collide(&L->p, f, s, t, fo);
         if (rc != FLBREF_OK) {
-          L->err_step = (int64_t)t;
-          return rc;
+#pragma omp critical(flbref_bad_site)
+          if (s < first_bad) {
+            first_bad = s;
+            first_rc = rc;
+          }
         }
         for (int i = 0; i < 9; ++i) L->fpost[i * n + s] = fo[i];
       }
+    if (first_bad < n) {
+      L->err_step = (int64_t)t;
+      return first_rc;
+    }
     for (int i = 0; i < 9; ++i)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {

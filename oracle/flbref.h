@@ -80,6 +80,9 @@ int flbref_collide_lut_at(const flbref_params* p, const double f[9], uint64_t si
                           uint64_t step, int32_t ix, int32_t iy, double fout[9]);
 
 /* ---- lattice ---- */
+/* Threads of the lattice calls' per-site loops (default 1; results are the
+ * same for any count). */
+void flbref_set_threads(int n);
 int flbref_lattice_create(const flbref_params* p, flbref_lattice** out);
 int flbref_lattice_set_fields(flbref_lattice* L, const double* rho, const double* ux,
                               const double* uy);

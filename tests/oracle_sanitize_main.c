@@ -159,6 +159,9 @@ static void d3q19_calls(int basis) {
 
 int main(void) {
   d2q9_site_calls();
+  flbref_set_threads(3);
+  d2q9_lattice(FLBREF_BASIS_FNORM_LOCAL, FLBREF_INIT_THERMAL, 8, 6);
+  flbref_set_threads(1);
   for (int b = 0; b < 3; ++b)
     for (int init = 0; init < 3; ++init) {
       d2q9_lattice(b, init, 8, 4);

@@ -543,3 +543,27 @@ def test_sk_fields_and_single_sample_structure_factor():
                 (B * Cc.conjugate()).imag]
         for w in range(5):
             assert abs(S[w][ky, kx] - want[w] / (nx * ny)) < 1e-12 * (abs(A) ** 2 + 1e-3), (w, kx, ky)
+
+
+def test_oracle_threads_do_not_change_results():
+    """The lattice calls' per-site loops may run on several threads; every
+    result (populations, correlators, structure factors) is bit-identical
+    to the single-threaded run."""
+    kw = dict(ux0=0.1, uy0=-0.02, kT=1e-4, tau=[0.7, 0.9, 1.1, 1.3, 0.8, 1.2], seed=5,
+              sample_every=1, sk_every=2, block_steps=5)
+    out = []
+    for n in (1, 4):
+        O.set_threads(n)
+        try:
+            L = O.Lattice(O.make_params(24, 20, **kw))
+            L.step(21)
+            out.append((L.populations(), L.covariance(), L.structure_factor(0),
+                        L.structure_factor(3)))
+        finally:
+            O.set_threads(1)
+    a, b = out
+    np.testing.assert_array_equal(a[0], b[0])
+    for k in ("cov_f", "se_cov_f", "mean_df"):
+        np.testing.assert_array_equal(a[1][k], b[1][k])
+    np.testing.assert_array_equal(a[2], b[2])
+    np.testing.assert_array_equal(a[3], b[3])

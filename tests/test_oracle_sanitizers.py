@@ -18,7 +18,7 @@ def test_oracle_runs_clean_under_sanitizers(tmp_path):
     exe = tmp_path / "oracle_sanitize"
     sanitize = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                 "-fno-omit-frame-pointer"]
-    cmd = ["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-Wall", *sanitize,
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-Wall", "-fopenmp", *sanitize,
            "-I", ORACLE, os.path.join(ROOT, "tests", "oracle_sanitize_main.c"),
            os.path.join(ORACLE, "flbref.c"), os.path.join(ORACLE, "flbref3.c"),
            "-o", str(exe), "-lm"]
