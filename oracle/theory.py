@@ -175,3 +175,35 @@ def fit_lq(us, values):
     X = np.stack([us, us ** 2], axis=1)
     coef, *_ = np.linalg.lstsq(X, np.asarray(values, dtype=float), rcond=None)
     return coef[0], coef[1]
+
+
+# Bands of wavevectors for averaging structure factors: |m| in [lo, hi) with
+# m = (mx, my) the integer wavevector taken in [-n/2, n/2); "axis" bands
+# keep only my = 0 (the cut along k_x of the paper's figures).  The k = 0
+# mode and, for even sides, the staggered (n/2, 0) and (0, n/2) modes (exact
+# invariants, never excited) are left out, and so is |m| < 2: on a 256-wide
+# lattice those hydrodynamic modes decorrelate over ~5000 steps, too slowly
+# for errors from blocks of that length.
+PLANE_EDGES = (2, 4, 8, 16, 32, 64, 128, 200)
+AXIS_EDGES = (2, 4, 16, 64, 129)
+
+
+def band_masks(nx: int, ny: int, edges=PLANE_EDGES, axis: bool = False):
+    """Boolean masks [ky, kx], one per band."""
+    mx = np.fft.fftfreq(nx, 1.0 / nx)
+    my = np.fft.fftfreq(ny, 1.0 / ny)
+    MX, MY = np.meshgrid(mx, my)
+    r = np.hypot(MX, MY)
+    keep = r > 0
+    if nx % 2 == 0:
+        keep &= ~((np.abs(MX) == nx // 2) & (MY == 0))
+    if ny % 2 == 0:
+        keep &= ~((MX == 0) & (np.abs(MY) == ny // 2))
+    if axis:
+        keep &= MY == 0
+    return [keep & (r >= lo) & (r < hi) for lo, hi in zip(edges[:-1], edges[1:])]
+
+
+def band_means(S: np.ndarray, masks) -> np.ndarray:
+    """Mean of S[ky, kx] over each band."""
+    return np.array([S[m].mean() for m in masks])

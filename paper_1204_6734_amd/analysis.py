@@ -12,10 +12,16 @@
 - ``structure_factor_maps``: S_k of rho, j~_x, j~_y and the cross
   correlator R_k of eqs. (24)-(26), normalised by mu rho0 so that the ideal
   gas gives S = 1, R = 0 (Figs. 10 and 19-21).
+- ``mixed_tau_statistics``: one long run of a lattice with the statistics
+  of Sec. IV switched on (moment covariances every step, structure factors
+  every few steps), with the structure factors kept per time segment so
+  that their standard errors can be formed by blocking.
 
 Nothing here computes the method itself: the lattices run through libflb.
 """
 from __future__ import annotations
+
+import time
 
 import numpy as np
 
@@ -159,3 +165,44 @@ def structure_factor_maps(L, kT: float, rho0: float = 1.0) -> dict:
            for name, w in (("rho", 0), ("jx", 1), ("jy", 2))}
     out["R"] = (L.structure_factor(3) + 1j * L.structure_factor(4)) / mu_rho
     return out
+
+
+def mixed_tau_statistics(F, precision: int, ux0: float, nx: int = 256, ny: int = 256,
+                         kT: float = 1e-4, tau=None, seed: int = 1, therm: int = 20_000,
+                         steps: int = 100_000, sk_every: int = 10, segments: int = 20,
+                         block_steps: int = 5_000, basis: int = 0) -> dict:
+    """A periodic nx x ny lattice at rest density 1 in background flow
+    (u_x0, 0): ``therm`` steps from equilibrium, then ``steps`` steps sampling
+    the correlators every step (time blocks of ``block_steps``) and the
+    structure factors every ``sk_every`` steps.  Returns the library's
+    covariance readout ("cov") and the structure factors of each of
+    ``segments`` equal time segments ("sk_segments", shape (segments, 5, ny,
+    nx): rho, j~_x, j~_y, Re and Im of the cross term, each <|dA(k)|^2> /
+    (nx ny)), plus the wall time of the sampled steps."""
+    if tau is None:
+        from . import inputs
+        tau = inputs.mixed_taus(2)
+    if therm % sk_every or steps % (segments * sk_every):
+        raise ValueError("therm and steps / segments must be multiples of sk_every")
+    p = F.make_params(nx, ny, precision=precision, basis=basis, rho0=1.0, ux0=ux0, kT=kT,
+                      tau=tau, seed=seed, sample_every=1, block_steps=block_steps,
+                      sk_every=sk_every)
+    L = F.Lattice(p)
+    L.step(therm)
+    L.reset_stats()
+    seg = steps // segments
+    per = seg // sk_every  # structure-factor samples per segment
+    sums_prev = np.zeros((5, ny, nx))
+    out = np.empty((segments, 5, ny, nx))
+    t0 = time.perf_counter()
+    for s in range(segments):
+        L.step(seg)
+        sums = np.stack([L.structure_factor(w) for w in range(5)]) * ((s + 1) * per)
+        out[s] = (sums - sums_prev) / per
+        sums_prev = sums
+    L.sync()
+    dt = time.perf_counter() - t0
+    cov = L.covariance()
+    L.close()
+    return {"cov": cov, "sk_segments": out, "seconds": dt, "nx": nx, "ny": ny, "steps": steps,
+            "therm": therm, "ux0": ux0, "kT": kT, "tau": list(tau), "seed": seed}
