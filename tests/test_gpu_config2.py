@@ -1,0 +1,132 @@
+"""The 256 x 256 mixed-relaxation-time statistics workload on the GPU.
+
+Workload: periodic 256 x 256, rho0 = 1, u0 = (u, 0) for u in {0, 0.1, 0.2},
+kT = 1e-4, the six relaxation times of ``inputs.mixed_taus(2)`` (one uniform
+draw in [0.6, 1.5] per non-conserved mode), Philox seed 1; 2e4 steps from
+the equilibrium start, then 1e5 steps with the correlators sampled every
+step (20 time blocks of 5000) and the structure factors every 10 steps
+(kept per 5000-step segment for their blocking errors).  FP64 and
+FP32-shifted storage.
+
+What fixes the expected values (Sec. II eqs. (11)-(16), Sec. IV eqs. (23)-(26)):
+1. The oracle, independently: its FP64 run of the same workload with
+   Philox seed 2 (1e4 sampled steps after 2e4, tests/golden/config2_oracle.json,
+   written by tests/golden/make_config2.py) agrees with the GPU within the
+   combined standard errors, for the 45 unique entries of <dM~ dM~> (f-norm
+   at u0) and of <df df>.
+2. FP32-shifted storage reproduces the FP64 run (same noise) path by path:
+   every correlator within 1e-2 of its standard error.
+3. The linear-response theory (per-wavevector Lyapunov solution,
+   tests/golden/config2_theory.json).  At kT = 1e-4 the correlators differ
+   from it by the O(kT) correction of the nonlinear terms (u^2 in f^0, the
+   local density in the noise, the local basis), which these statistics
+   resolve (tens of standard errors).  A run at kT = 1e-3 (seed 3) measures
+   that correction: divided by the temperature it is the same at both, so
+   (C - C_lin) at 1e-4 equals a tenth of its value at 1e-3 within the
+   combined standard errors.  The structure factors S_k(rho~), S_k(j~_x),
+   S_k(j~_y) and R_k, averaged over bands of |k|, agree with the theory
+   within their blocking errors.
+"Within" means: every unique entry within 4.5 standard errors, at least 90 %
+within 3, and an rms z-score between 0.5 and 1.6.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import theory as T
+from paper_1204_6734_amd import analysis as A
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+U0 = ["0", "0.1", "0.2"]
+IU = np.triu_indices(9)
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+def zcheck(z, what):
+    z = np.asarray(z).ravel()
+    zmax, zrms, frac3 = np.abs(z).max(), math.sqrt((z ** 2).mean()), (np.abs(z) < 3).mean()
+    print(f"{what}: max|z| {zmax:.2f} rms {zrms:.2f} within3 {frac3:.2f}")
+    assert zmax < 4.5 and 0.5 < zrms < 1.6 and frac3 >= 0.9, (what, zmax, zrms, frac3)
+
+
+_runs = {}
+
+
+def run(flb, prec, u, kT=1e-4, seed=1):
+    key = (prec, u, kT, seed)
+    if key not in _runs:
+        precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+        _runs[key] = A.mixed_tau_statistics(flb, precision, float(u), kT=kT, seed=seed)
+    return _runs[key]
+
+
+@pytest.mark.parametrize("u", U0)
+def test_config2_agrees_with_the_oracle(flb, u):
+    r = run(flb, "fp64", u)
+    o = golden("config2_oracle.json")[u]
+    c = r["cov"]
+    assert c["nsamples"] == 256 * 256 * 100_000 and c["nblocks"] == 20
+    for mine, se, theirs, tse in (("cov_m_fnorm_u0", "se_cov_m", "cov_m_fnorm_u0", "se_cov_m"),
+                                  ("cov_f", "se_cov_f", "cov_f", "se_cov_f")):
+        want = np.array(o[theirs]).reshape(9, 9)
+        sw = np.array(o[tse]).reshape(9, 9)
+        z = (c[mine] - want) / np.sqrt(c[se] ** 2 + sw ** 2)
+        zcheck(z[IU], f"u0 {u}: GPU {mine} vs oracle (seed 2)")
+
+
+@pytest.mark.parametrize("u", U0)
+def test_config2_fp32_reproduces_fp64(flb, u):
+    a, b = run(flb, "fp64", u), run(flb, "fp32", u)
+    for k, se in (("cov_m_fnorm_u0", "se_cov_m"), ("cov_f", "se_cov_f")):
+        d = (np.abs(a["cov"][k] - b["cov"][k]) / a["cov"][se])[IU].max()
+        print(f"u0 {u}: FP32 - FP64 {k}: max {d:.4f} standard errors")
+        assert d < 1e-2, (k, d)
+    sa, sb = a["sk_segments"].mean(axis=0)[:3], b["sk_segments"].mean(axis=0)[:3]
+    rel = np.abs(sa - sb).max() / np.abs(sa).max()
+    print(f"u0 {u}: FP32 - FP64 structure factors: max {rel:.2e} of the largest")
+    assert rel < 1e-5
+
+
+@pytest.mark.parametrize("u", U0)
+def test_config2_linear_theory_and_its_O_kT_correction(flb, u):
+    th = golden("config2_theory.json")[u]
+    lin = np.array(th["cov_m"]).reshape(9, 9)
+    a = run(flb, "fp64", u)["cov"]
+    b = run(flb, "fp64", u, kT=1e-3, seed=3)["cov"]
+    ra, sa = a["cov_m_fnorm_u0"] - lin, a["se_cov_m"]
+    rb, sb = (b["cov_m_fnorm_u0"] / 10 - lin), b["se_cov_m"] / 10  # per 1e-4 of kT
+    za = (ra / sa)[IU]
+    print(f"u0 {u}: kT 1e-4 vs linear theory: rms z {math.sqrt((za ** 2).mean()):.1f} "
+          "(the resolved O(kT) correction)")
+    # the deviation is the O(kT) term: ten times larger (per unit kT) at 1e-3
+    zcheck(((ra - rb / 10) / np.sqrt(sa ** 2 + (sb / 10) ** 2))[IU],
+           f"u0 {u}: (C - C_lin) at 1e-4 minus a tenth of it at 1e-3")
+    big = np.abs(rb[IU]) > 30 * sb[IU]
+    ratio = np.median(rb[IU][big] / ra[IU][big])
+    print(f"u0 {u}: median ratio of the deviations (1e-3 / 1e-4 per unit kT) over "
+          f"{big.sum()} entries: {ratio:.2f}")
+    assert big.sum() >= 5 and 8.0 < ratio < 12.0
+
+
+@pytest.mark.parametrize("u", U0)
+def test_config2_structure_factor_bands_match_theory(flb, u):
+    th = golden("config2_theory.json")[u]
+    segs = run(flb, "fp64", u)["sk_segments"]
+    z = []
+    for edges, axis, key in ((T.PLANE_EDGES, False, "sk_plane"),
+                             (T.AXIS_EDGES, True, "sk_axis")):
+        masks = T.band_masks(256, 256, edges, axis=axis)
+        for w, name in enumerate(("rho", "jx", "jy", "jxjy_re")):
+            per = np.array([T.band_means(segs[s, w], masks) for s in range(segs.shape[0])])
+            m, se = per.mean(axis=0), per.std(axis=0, ddof=1) / math.sqrt(per.shape[0])
+            z.append((m - np.array(th[key][name])) / se)
+    zcheck(np.concatenate(z), f"u0 {u}: S_k(rho~), S_k(j~_x), S_k(j~_y), R_k bands vs theory")
