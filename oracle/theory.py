@@ -96,34 +96,40 @@ def _doubling(T: np.ndarray, Q: np.ndarray, n: int = 24) -> np.ndarray:
     return c
 
 
-def k_covariances(p: "O.Params", A: np.ndarray | None = None, Q: np.ndarray | None = None):
-    """c(k) for every lattice wavevector, shape (ny, nx, 9, 9), index [ky, kx]."""
+def k_covariances_at(p: "O.Params", kx_idx, ky_idx, A: np.ndarray | None = None,
+                     Q: np.ndarray | None = None) -> np.ndarray:
+    """c(k) at the wavevectors k = 2 pi (kx_idx / nx, ky_idx / ny) (integer
+    index arrays of one shape), shape (..., 9, 9)."""
     vx, vy, _ = O.velocities()
     A = jacobian(p) if A is None else A
     Q = noise_matrix(p) if Q is None else Q
-    nx, ny = p.nx, p.ny
-    kx = 2 * np.pi * np.arange(nx) / nx
-    ky = 2 * np.pi * np.arange(ny) / ny
-    KX, KY = np.meshgrid(kx, ky)  # [ky, kx]
-    ph = np.exp(-1j * (KX[..., None] * vx + KY[..., None] * vy))  # (ny, nx, 9)
-    T = ph[..., :, None] * A[None, None, :, :]
-    Qk = ph[..., :, None] * Q[None, None] * ph.conj()[..., None, :]
-    out = np.zeros((ny, nx, 9, 9), dtype=complex)
-    eig = np.abs(np.linalg.eigvals(T.reshape(-1, 9, 9))).max(axis=-1).reshape(ny, nx)
+    KX = 2 * np.pi * np.asarray(kx_idx, dtype=float) / p.nx
+    KY = 2 * np.pi * np.asarray(ky_idx, dtype=float) / p.ny
+    shape = KX.shape
+    ph = np.exp(-1j * (KX.reshape(-1)[:, None] * vx + KY.reshape(-1)[:, None] * vy))  # (n, 9)
+    T = ph[:, :, None] * A[None, :, :]
+    Qk = ph[:, :, None] * Q[None] * ph.conj()[:, None, :]
+    out = np.zeros((len(ph), 9, 9), dtype=complex)
+    eig = np.abs(np.linalg.eigvals(T)).max(axis=-1)
     singular = eig > 1 - 1e-9
     # regular wavevectors: vec(c) = (I - conj(T) (x) T)^-1 vec(Q) (row-major vec)
-    reg = np.argwhere(~singular)
+    reg = np.flatnonzero(~singular)
     eye = np.eye(81)
     for start in range(0, len(reg), 4096):
         idx = reg[start:start + 4096]
-        Tb = T[idx[:, 0], idx[:, 1]]
-        Qb = Qk[idx[:, 0], idx[:, 1]]
+        Tb = T[idx]
         K = np.einsum("nij,nkl->nikjl", Tb, Tb.conj()).reshape(-1, 81, 81)
-        sol = np.linalg.solve(eye[None] - K, Qb.reshape(-1, 81, 1))
-        out[idx[:, 0], idx[:, 1]] = sol.reshape(-1, 9, 9)
-    for iy, ix in np.argwhere(singular):
-        out[iy, ix] = _doubling(T[iy, ix], Qk[iy, ix])
-    return out
+        sol = np.linalg.solve(eye[None] - K, Qk[idx].reshape(-1, 81, 1))
+        out[idx] = sol.reshape(-1, 9, 9)
+    for n in np.flatnonzero(singular):
+        out[n] = _doubling(T[n], Qk[n])
+    return out.reshape(*shape, 9, 9)
+
+
+def k_covariances(p: "O.Params", A: np.ndarray | None = None, Q: np.ndarray | None = None):
+    """c(k) for every lattice wavevector, shape (ny, nx, 9, 9), index [ky, kx]."""
+    KX, KY = np.meshgrid(np.arange(p.nx), np.arange(p.ny))  # [ky, kx]
+    return k_covariances_at(p, KX, KY, A, Q)
 
 
 def site_covariance(p: "O.Params", ck=None) -> np.ndarray:
@@ -157,7 +163,8 @@ def moment_covariance(p: "O.Params", C: np.ndarray, basis: str = "fnorm_u0") -> 
 
 
 def structure_factors(p: "O.Params", ck=None) -> dict:
-    """Predicted <|dA(k)|^2>/(nx ny) for rho, j~_x, j~_y at u0 and the cross term."""
+    """Predicted <|dA(k)|^2>/(nx ny) for rho, j~_x, j~_y at u0 and the cross term
+    (for every wavevector, or for the c(k) given)."""
     ck = k_covariances(p) if ck is None else ck
     B = O.fnorm_basis(p.ux0, p.uy0)
     b0 = np.ones(9)

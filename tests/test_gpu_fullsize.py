@@ -172,3 +172,42 @@ def test_largest_fp64_lattice_sampled_sites_by_rows(flb):
     n = 21824
     assert 9 * n * n < 2 ** 32 and 9 * (n + 1) * (n + 64) >= 2 ** 32
     sampled_sites_by_rows(flb, n, n, flb.FP64, 1e-14, "21824^2 FP64")
+
+
+def test_8192_fp32_transverse_spectrum_matches_theory(flb):
+    """The noisy spectrum of the large shear-wave lattice (8192^2 FP32-shifted,
+    u_x0 = 0.1, kT = 1e-4, tau = 1): S_k(j~_y), S_k(j~_x) and S_k(rho~) along
+    k_x (k_y = 0; eqs. (24)-(25), the transverse-momentum spectrum being
+    S_k(j~_y)) sampled every 100 steps from step 2000 to 10000, against the
+    linear-response theory at the same wavevectors.  Bands of wavenumber
+    index [256, 512), [512, 1024), [1024, 2048), [2048, 4096): waves of at
+    most 32 sites, which relax within tens of steps (the long waves are not
+    thermalised within 1e4 steps).  Per band, the mean of S_gpu(k) / S_th(k)
+    is 1 within its standard error (from the spread over the band's
+    wavevectors, which fluctuate independently)."""
+    from oracle import theory as T
+    nx = 8192
+    kw = dict(ux0=0.1, kT=1e-4, seed=1)
+    L = flb.Lattice(flb.make_params(nx, nx, precision=flb.FP32_SHIFTED, init=flb.INIT_FIELDS,
+                                    sk_every=100, **kw))
+    L.set_fields(*I.shear_wave_fields(nx, nx, ux0=0.1, amp=1e-3))
+    L.step(2000)
+    L.reset_stats()
+    L.step(8000)
+    rows = {w: L.structure_factor(w)[0, :4096].copy() for w in (0, 1, 2)}
+    L.close()
+    kx = np.arange(4096)
+    ck = T.k_covariances_at(O.make_params(nx, nx, **kw), kx, np.zeros_like(kx))
+    th = T.structure_factors(O.make_params(nx, nx, **kw), ck)
+    z = []
+    for w, name in ((0, "rho"), (1, "jx"), (2, "jy")):
+        for lo, hi in ((256, 512), (512, 1024), (1024, 2048), (2048, 4096)):
+            r = rows[w][lo:hi] / th[name][lo:hi]
+            m, se = r.mean(), r.std(ddof=1) / math.sqrt(hi - lo)
+            z.append((m - 1) / se)
+            print(f"S_k({name}) along k_x, [{lo}, {hi}): mean ratio to theory {m:.4f} "
+                  f"+- {se:.4f}")
+    z = np.array(z)
+    zmax, zrms = np.abs(z).max(), math.sqrt((z ** 2).mean())
+    print(f"8192^2 spectrum vs theory: max|z| {zmax:.2f} rms {zrms:.2f}")
+    assert zmax < 4.5 and 0.3 < zrms < 1.6, (zmax, zrms)
