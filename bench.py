@@ -193,6 +193,14 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                 log.append(L.fourier_mode(2, 1, 0))
         return log
 
+    # the two bandwidth probes (the step's access pattern without arithmetic,
+    # and a plain contiguous copy of the same bytes) run before the timed
+    # steps: a second of full-bandwidth traffic also brings the device to its
+    # sustained clocks, which a few warm-up steps alone do not
+    bps = BYTES_PER_SITE["f32" if fp32 else "f64"]
+    probes = {"copy_ms": F.copy_probe(nx, nx, F.FP32_SHIFTED if fp32 else F.FP64, reps=20),
+              "stream_bytes": bps // 2 * nx * nx}
+    probes["stream_ms"] = F.stream_copy_probe(probes["stream_bytes"], reps=20)
     run(warmup)
     L.sync()
     torch.cuda.synchronize()
@@ -227,7 +235,7 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                    "ms_per_step": round(dt1 * 1e3 / every, 4),
                    "mlups": round(sites * every / dt1 / 1e6, 1)}
     return {"sites": sites, "dt": dt, "kernel_ms": kms / max(launches, 1), "launches": launches,
-            "mode_log": [abs(z) for z in log[-3:]],
+            "mode_log": [abs(z) for z in log[-3:]], "probes": probes,
             "sk_in_window": n_sk, "mode_logs_in_window": len(log), "with_sk": with_sk,
             "launch": {"chosen": L.get_launch(), "candidates": tune},
             "config": {"workload": f"{nx}x{nx} D2Q9 {'FP32-shifted' if fp32 else 'FP64'}, "
@@ -511,11 +519,9 @@ def main():
     # the step's memory traffic with no arithmetic (same layout, tiles and
     # addressing): the practical ceiling of its access pattern; and a plain
     # contiguous copy of the population bytes: the device's streaming ceiling
-    fp32 = r["dtype"] == "f32"
-    copy_ms = F.copy_probe(args.nx, args.nx, F.FP32_SHIFTED if fp32 else F.FP64, reps=20)
+    copy_ms = r["probes"]["copy_ms"]
     copy_gbps = bps * r["sites"] / (copy_ms * 1e-3) / 1e9
-    stream_bytes = bps // 2 * r["sites"]
-    stream_ms = F.stream_copy_probe(stream_bytes, reps=20)
+    stream_bytes, stream_ms = r["probes"]["stream_bytes"], r["probes"]["stream_ms"]
     stream_gbps = 2 * stream_bytes / (stream_ms * 1e-3) / 1e9
     out = {
         "metric": "fluct. D2Q9 MLUPS, % of HBM roofline; served solves/s + p99 latency",

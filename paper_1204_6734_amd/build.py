@@ -3,7 +3,11 @@
     python -m paper_1204_6734_amd.build        # or build() from Python
 
 Every HIP source is compiled with packed-FP32 instruction selection turned
-off (those instructions are not used by this library).
+off (those instructions are not used by this library), and with
+multiply-adds fused only where one source expression holds both
+(-ffp-contract=on): the rounding of every result is then fixed by the
+source, so the kernel variants that share the collision (with and without
+the correlator sums, for instance) produce bit-identical populations.
 """
 from __future__ import annotations
 
@@ -33,7 +37,7 @@ def hipcc() -> str:
 def compile_flags() -> list[str]:
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-munsafe-fp-atomics", "-I", INCLUDE, "-I", CSRC,
+            "-ffp-contract=on", "-munsafe-fp-atomics", "-I", INCLUDE, "-I", CSRC,
             "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 

@@ -168,9 +168,14 @@ __device__ __forceinline__ void back3(const R y[15], R sg[19]) {
 // local-density factor of the amplitudes of eq. (20).
 template <typename R>
 __device__ __forceinline__ void scaled_noise(int noise, R rho, const R Nu[15], R N[15]) {
-  const R sr = noise ? rho * rsqrt_t(rho) : R(0);
+  if (noise) {
+    const R sr = rho * rsqrt_t(rho);
 #pragma unroll
-  for (int a = 0; a < 15; ++a) N[a] = Nu[a] * sr;
+    for (int a = 0; a < 15; ++a) N[a] = Nu[a] * sr;
+  } else {
+#pragma unroll
+    for (int a = 0; a < 15; ++a) N[a] = R(0);
+  }
 }
 
 // The collision in the fixed Hermite-type rows with n = w m (BASIS 1), on
@@ -507,40 +512,37 @@ step3_kernel(const Desc3* __restrict__ desc, const uint64_t* __restrict__ clock,
   const bool active = x < d.nx && y < d.ny;
   const uint32_t N = (uint32_t)d.nx * d.ny * d.nz;
   constexpr uint32_t E = sizeof(S);
-  const uint32_t xc = (uint32_t)x * E;
+  // offsets of the site clamped onto the lattice: the lanes and wavefronts
+  // of a ragged last tile load a real site's values (which they never use),
+  // so the loads need no branch
+  const int xl = x < d.nx ? x : d.nx - 1, yl = y < d.ny ? y : d.ny - 1;
+  const uint32_t xc = (uint32_t)xl * E;
   uint32_t xm = xc - E, xp = xc + E;
   if (ODD && (tx == 0 || tx == d.tiles_x - 1)) {
     // wave-uniform: only the wavefronts at the two ends of a row wrap
     asm volatile("" : "+v"(xm), "+v"(xp));
-    xm = x == 0 ? (uint32_t)(d.nx - 1) * E : xm;
-    xp = x == d.nx - 1 ? 0u : xp;
+    xm = xl == 0 ? (uint32_t)(d.nx - 1) * E : xm;
+    xp = xl == d.nx - 1 ? 0u : xp;
   }
   uint32_t voff[19], soff[19];
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const int cx = ODD ? kC3[i][0] : 0, cy = ODD ? kC3[i][1] : 0, cz = ODD ? kC3[i][2] : 0;
     voff[i] = cx > 0 ? xm : (cx < 0 ? xp : xc);
-    const int ys = cy == 0 ? y : wrap(y - cy, d.ny), zs = cz == 0 ? z : wrap(z - cz, d.nz);
+    const int ys = cy == 0 ? yl : wrap(yl - cy, d.ny), zs = cz == 0 ? z : wrap(z - cz, d.nz);
     soff[i] = ((uint32_t)zs * d.ny + (uint32_t)ys) * (uint32_t)d.nx * E;
   }
   R h[19];
-  if (active) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i)
-      h[i] = (R)buf_load(plane_rsrc<S>(d.pop, N, ODD ? kOpp3[i] : i), voff[i], soff[i],
-                         (S*)nullptr);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 19; ++i) h[i] = R(0);
-  }
+  for (int i = 0; i < 19; ++i)
+    h[i] = (R)buf_load(plane_rsrc<S>(d.pop, N, ODD ? kOpp3[i] : i), voff[i], soff[i],
+                       (S*)nullptr);
   // the unit Gaussians need only the site and the step: drawn here, while
   // the loads are still in flight, they cover part of the load latency
   // (measured faster for every variant but the FP32 Hermite-row one, which
   // is memory-bound and keeps drawing them inside its collision)
   constexpr bool kEarlyNoise = !(sizeof(R) == 4 && BASIS == 1);
-  R Nu[15];
-#pragma unroll
-  for (int a = 0; a < 15; ++a) Nu[a] = R(0);
+  R Nu[15];  // read by the collision only where drawn
   if (kEarlyNoise && d.noise && active) gaussians15<R>(d.k0, d.k1, cell(x, y, z, d), t, R(1), Nu);
   if (SAMPLE) {
     if (d.sample_every > 0 && t % (uint64_t)d.sample_every == 0)

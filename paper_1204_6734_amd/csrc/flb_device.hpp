@@ -308,23 +308,23 @@ __device__ __forceinline__ Moments<R> hermite_moments(const R h[9]) {
 // sigma_i = sum_{a=3..8} m_i^a Y_a for the Hermite rows of eq. (A3).
 template <typename R>
 __device__ __forceinline__ void hermite_back(const R Y[6], R s[9]) {
+  // written so that each product sits in the expression that adds it (one
+  // fused multiply-add per term)
   constexpr R S32 = R(1.2247448713915890491), S6 = R(2.4494897427831780982);
   const R base = R(0.5) * Y[2] - Y[5];
-  const R t3 = R(1.5) * Y[0];
-  const R q6 = S32 * Y[3], q7 = S32 * Y[4];
+  const R bp = base + R(1.5) * Y[0], bm = base - R(1.5) * Y[0];
   s[0] = R(0.5) * Y[5] - Y[2];
-  s[1] = (base + t3) - q6;
-  s[3] = (base + t3) + q6;
-  s[2] = (base - t3) - q7;
-  s[4] = (base - t3) + q7;
+  s[1] = bp - S32 * Y[3];
+  s[3] = bp + S32 * Y[3];
+  s[2] = bm - S32 * Y[4];
+  s[4] = bm + S32 * Y[4];
   const R db = R(2) * (Y[2] + Y[5]);
-  const R e = R(3) * Y[1];
-  const R p6 = S6 * Y[3], p7 = S6 * Y[4];
-  const R dp = db + e, dm = db - e;
-  s[5] = dp + (p6 + p7);
-  s[7] = dp - (p6 + p7);
-  s[6] = dm - (p6 - p7);
-  s[8] = dm + (p6 - p7);
+  const R dp = db + R(3) * Y[1], dm = db - R(3) * Y[1];
+  const R q = Y[3] + Y[4], r = Y[3] - Y[4];
+  s[5] = dp + S6 * q;
+  s[7] = dp - S6 * q;
+  s[6] = dm - S6 * r;
+  s[8] = dm + S6 * r;
 }
 
 // g_i = f_i^0(1, u) of eq. (A1).
@@ -510,11 +510,14 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, const R
   const R* d = S.d;
 
   // sqrt(rho) N: the local-density factor of the amplitudes of eq. (20)
-  R N[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  R N[6];
   if (C.noise) {
     const R sr = S.rho * rsqrt_t(S.rho);
 #pragma unroll
     for (int a = 0; a < 6; ++a) N[a] = Nu[a] * sr;
+  } else {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) N[a] = R(0);
   }
 
   if (BASIS == kBasisHermite) {

@@ -325,15 +325,22 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   const bool active = live && (x < nx) && (y < ny);
   const uint32_t N = (uint32_t)nx * (uint32_t)ny;
 
+  // The offsets are computed outside the per-lane branch (they are only
+  // arithmetic): the row resources and plane offsets then stay wave-uniform
+  // in scalar registers up to the stores, which need them there.  They are
+  // those of the site clamped onto the lattice, so that the lanes and
+  // wavefronts of a ragged last tile load a real site's values (which they
+  // never use) and the plain step's loads need no branch.
   __amdgpu_buffer_rsrc_t rs[9];
   uint32_t voff[9], soff[9];
+  site_offsets<S, ODD>(sd.pop, sd.pitch, x < nx ? x : nx - 1, y < ny ? y : ny - 1, nx, ny,
+                       xw == 0 || xw + kTileX >= nx, rs, voff, soff);
   R h[9];
-  if (active) {
-    site_offsets<S, ODD>(sd.pop, sd.pitch, x, y, nx, ny, xw == 0 || xw + kTileX >= nx, rs, voff,
-                         soff);
+  if (!SAMPLE || active) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) h[i] = (R)buf_load(rs[i], voff[i], soff[i], (S*)nullptr);
   } else {
+    // the correlator sums take the sites off the lattice as zeros
 #pragma unroll
     for (int i = 0; i < 9; ++i) h[i] = R(0);
   }
@@ -342,7 +349,7 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   const uint32_t site = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
   // the Gaussians need only the site and the step: drawn here, while the
   // loads are still in flight, they cover part of the load latency
-  R Nu[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  R Nu[6];  // read by the collision only where drawn
   if (active && C.noise) unit_gaussians<R, (sizeof(S) < sizeof(R))>(C, site, t, Nu);
 
   bool due = false;
