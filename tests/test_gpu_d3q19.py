@@ -87,16 +87,47 @@ def test_degenerate_shapes_match_oracle(flb, shape):
         assert np.abs(fg - fo).max() <= 1e-12 * np.abs(fo).max(), (shape, o.t)
 
 
-def test_fp32_shifted_matches_fp64_oracle(flb):
-    nx, ny, nz = 40, 8, 6
-    kw = dict(ux0=0.1, uy0=0.05, uz0=0.0, kT=1e-4, tau=TAUS, seed=3)
-    g, o = both(flb, nx, ny, nz, flb.FP32_SHIFTED, flb.BASIS_FNORM_LOCAL, **kw)
+@pytest.mark.parametrize("basis", ["fnorm", "hermite"])
+def test_fp32_shifted_matches_fp64_oracle(flb, basis):
+    """FP32-shifted storage with the FP32 collision of either basis (the
+    Hermite-type rows draw their Gaussians inside the collision, with the
+    local density in the Box-Muller radius): the fluctuations f - f^0(rho0,
+    u0) after 200 steps to 1e-5 of their largest value, at 70 x 8 x 6 (a
+    ragged second tile along x)."""
+    b = flb.BASIS_FNORM_LOCAL if basis == "fnorm" else flb.BASIS_HERMITE
+    nx, ny, nz = 70, 8, 6
+    kw = dict(ux0=0.1, uy0=0.05, uz0=-0.02, kT=1e-4, tau=TAUS, seed=3)
+    g, o = both(flb, nx, ny, nz, flb.FP32_SHIFTED, b, **kw)
     g.step(200)
     o.step(200)
-    f0 = D.equilibrium(1.0, 0.1, 0.05, 0.0)[:, None, None, None]
+    f0 = D.equilibrium(1.0, 0.1, 0.05, -0.02)[:, None, None, None]
     dg, do = g.populations() - f0, o.populations() - f0
     err = np.abs(dg - do).max() / np.abs(do).max()
-    assert err <= 1e-5, err
+    print(f"{basis}: max |df_gpu - df_oracle| / max |df| = {err:.2e}")
+    assert err <= 1e-5, (basis, err)
+
+
+@pytest.mark.parametrize("basis", ["fnorm", "hermite"])
+def test_fp32_correlator_sums_match_oracle(flb, basis):
+    """The correlator sums of an FP32-shifted lattice (values staged in FP32,
+    products and sums in FP64 on the matrix cores) against the oracle's FP64
+    run of the same noise: the stored deviations carry one FP32 rounding, so
+    the covariances agree to a few 1e-7 of their largest entry (bound 1e-6)
+    and the means to 1e-6 of the fluctuation amplitude sqrt(max_i C_ii)."""
+    b = flb.BASIS_FNORM_LOCAL if basis == "fnorm" else flb.BASIS_HERMITE
+    nx, ny, nz = 20, 5, 4
+    kw = dict(ux0=0.08, uy0=-0.02, kT=1e-4, tau=TAUS, seed=21, sample_every=1, block_steps=5)
+    g, o = both(flb, nx, ny, nz, flb.FP32_SHIFTED, b, **kw)
+    g.step(30)
+    o.step(30)
+    cg, co = g.covariance(), o.covariance()
+    assert cg["nsamples"] == co["nsamples"] == 30 * nx * ny * nz
+    assert cg["nblocks"] == co["nblocks"] == 6
+    err = np.abs(cg["cov_f"] - co["cov_f"]).max() / np.abs(co["cov_f"]).max()
+    sigma = math.sqrt(np.diag(co["cov_f"]).max())
+    merr = np.abs(cg["mean_df"] - co["mean_df"]).max() / sigma
+    print(f"{basis}: cov_f rel err {err:.2e}, mean_df err / sigma {merr:.2e}")
+    assert err <= 1e-6 and merr <= 1e-6, (basis, err, merr)
 
 
 def test_correlator_sums_match_oracle(flb):
