@@ -37,13 +37,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"f32": 72, "f64": 144}
 # D3Q19 FP32 f-norm step: VALU wavefront instructions per wavefront (= per
-# site), profiles/step3_fp32_256cube_d3q19.md
-D3Q19_VALU_PER_SITE = 2517
-# FP32 floating-point operations per site of that kernel: its FMAs (2 each:
-# 1340 v_fma + 280 v_fmac + 84 v_fmamk) and adds and multiplies (1 each: 309
-# v_mul + 101 v_add + 65 others) in the gfx950 code, 3883 in all
-# (profiles/step3_fp32_256cube_d3q19.md); one lane computes one site.
-D3Q19_FLOPS_PER_SITE = 3883
+# site), SQ_INSTS_VALU / SQ_WAVES averaged over both phases,
+# profiles/step3_fp32_256cube_d3q19.md
+D3Q19_VALU_PER_SITE = 2526
+# FP32 floating-point operations per site of that kernel, counted in its
+# gfx950 code: FMAs 2 each (1640 v_fma/v_fmac/v_fmamk), multiplies, adds and
+# subtracts 1 each (338 + 229), transcendentals (rsq, rcp, sqrt, log, sin,
+# cos) 1 each (50); conversions, compares and min/max are not counted.  One
+# lane computes one site.
+D3Q19_FLOPS_PER_SITE = 3897
 # FP32 vector peak without packed (two-wide) instructions, which this
 # library does not use: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9
