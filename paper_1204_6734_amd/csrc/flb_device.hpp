@@ -93,15 +93,26 @@ __device__ __forceinline__ void box_muller(uint32_t ua, uint32_t ub, R v, R& n0,
 // they agree with the correctly rounded values to ~1.3e-7 (absolute,
 // sin/cos) and ~1.2e-7 (relative, log), the same level as the library
 // routines.
+// The pieces of one pair: the squared radius of unit variance l = -2 ln ua
+// and the cosine and sine of the angle.
 template <int BITS>
-__device__ __forceinline__ void box_muller_f32(uint32_t ua, uint32_t ub, float v, float& n0,
-                                               float& n1) {
+__device__ __forceinline__ void box_muller_parts_f32(uint32_t ua, uint32_t ub, float& l,
+                                                     float& c, float& s) {
   constexpr float scale = 1.0f / (float)(1u << BITS), half = 0.5f / (float)(1u << BITS);
   const float fa = __fmaf_rn((float)ua, scale, half);
   const float fb = __fmaf_rn((float)ub, scale, half);
-  const float r = __builtin_amdgcn_sqrtf((-1.3862943611198906f * v) * __builtin_amdgcn_logf(fa));
-  n0 = r * __builtin_amdgcn_cosf(fb);
-  n1 = r * __builtin_amdgcn_sinf(fb);
+  l = -1.3862943611198906f * __builtin_amdgcn_logf(fa);
+  c = __builtin_amdgcn_cosf(fb);
+  s = __builtin_amdgcn_sinf(fb);
+}
+template <int BITS>
+__device__ __forceinline__ void box_muller_f32(uint32_t ua, uint32_t ub, float v, float& n0,
+                                               float& n1) {
+  float l, c, s;
+  box_muller_parts_f32<BITS>(ua, ub, l, c, s);
+  const float r = __builtin_amdgcn_sqrtf(v * l);
+  n0 = r * c;
+  n1 = r * s;
 }
 template <>
 __device__ __forceinline__ void box_muller<float, 21>(uint32_t ua, uint32_t ub, float v, float& n0,
@@ -220,17 +231,32 @@ __device__ __forceinline__ void box_muller<double, 24>(uint32_t ua, uint32_t ub,
 // Box-Muller on the pairs (u0,u1), (u2,u3), (u4,u5).  v = 1 gives unit
 // Gaussians (the collision's draw; it scales them by sqrt(rho), the
 // local-density factor of the noise amplitude of eq. (20)).
+// The six 21-bit integer pairs of one (site, step): counter (site, 0, step
+// lo, step hi ^ tag) (a lattice has < 2^32 sites), the top 21 bits of each
+// word and the low bits of words 0/2 joined with those of words 1/3.
+struct Uniform21 {
+  uint32_t a[3], b[3];
+};
+__device__ __forceinline__ Uniform21 site_uniforms(uint32_t k0, uint32_t k1, uint32_t site,
+                                                   uint64_t step, uint32_t tag) {
+  const uint4 w =
+      philox4x32_10_site(site, 0u, (uint32_t)step, (uint32_t)(step >> 32) ^ tag, k0, k1);
+  Uniform21 u;
+  u.a[0] = w.x >> 11;
+  u.b[0] = w.y >> 11;
+  u.a[1] = w.z >> 11;
+  u.b[1] = w.w >> 11;
+  u.a[2] = (w.x & 0x7FFu) | ((w.y & 0x3FFu) << 11);
+  u.b[2] = (w.z & 0x7FFu) | ((w.w & 0x3FFu) << 11);
+  return u;
+}
+
 template <typename R>
 __device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint32_t site,
                                                uint64_t step, uint32_t tag, R v, R N[6]) {
-  // counter (site, 0, step lo, step hi ^ tag): a lattice has < 2^32 sites
-  const uint4 w =
-      philox4x32_10_site(site, 0u, (uint32_t)step, (uint32_t)(step >> 32) ^ tag, k0, k1);
-  const uint32_t u4 = (w.x & 0x7FFu) | ((w.y & 0x3FFu) << 11);
-  const uint32_t u5 = (w.z & 0x7FFu) | ((w.w & 0x3FFu) << 11);
-  box_muller<R, 21>(w.x >> 11, w.y >> 11, v, N[0], N[1]);
-  box_muller<R, 21>(w.z >> 11, w.w >> 11, v, N[2], N[3]);
-  box_muller<R, 21>(u4, u5, v, N[4], N[5]);
+  const Uniform21 u = site_uniforms(k0, k1, site, step, tag);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) box_muller<R, 21>(u.a[k], u.b[k], v, N[2 * k], N[2 * k + 1]);
 }
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -480,41 +506,73 @@ __device__ __forceinline__ bool local_state(const R h[9], R rho0, R ux0, R uy0,
   return true;
 }
 
-// Unit Gaussians of one (site, step).  The draw needs only the site and the
+// The Gaussian draw of one (site, step).  It needs only the site and the
 // step, so the step kernel makes it before the populations of the site have
-// arrived; collide scales them by sqrt(rho).  NOISE32: draw in FP32 although
-// the collision runs in FP64 (FP32 storage above the FP32 basis speed: the
-// stored result is rounded to FP32 anyway, and the FP32 transform is a sixth
-// of the FP64 one's cost).
+// arrived; the collision scales it by sqrt(rho), the local-density factor of
+// the amplitudes of eq. (20).  FP32 keeps the Box-Muller pieces (squared
+// radius, cosine, sine) and forms the radius there as sqrt(rho l), which
+// folds that factor into the square root it takes anyway.  FP64 keeps unit
+// Gaussians; NOISE32 draws them in FP32 although the collision runs in FP64
+// (FP32 storage above the FP32 basis speed: the stored result is rounded to
+// FP32 anyway, and the FP32 transform is a sixth of the FP64 one's cost).
+template <typename R>
+struct SiteDraw {
+  R n[6];  // unit Gaussians
+};
+template <>
+struct SiteDraw<float> {
+  float l[3];   // -2 ln u of each pair
+  float cs[6];  // cosine, sine of each pair's angle
+};
+
 template <typename R, bool NOISE32>
-__device__ __forceinline__ void unit_gaussians(const CollideConst<R>& C, uint32_t site,
-                                               uint64_t t, R N[6]) {
-  if constexpr (NOISE32) {
+__device__ __forceinline__ void site_draw(const CollideConst<R>& C, uint32_t site, uint64_t t,
+                                          SiteDraw<R>& D) {
+  if constexpr (sizeof(R) == 4) {
+    const Uniform21 u = site_uniforms(C.k0, C.k1, site, t, 0u);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      box_muller_parts_f32<21>(u.a[k], u.b[k], D.l[k], D.cs[2 * k], D.cs[2 * k + 1]);
+  } else if constexpr (NOISE32) {
     float n32[6];
     site_gaussians<float>(C.k0, C.k1, site, t, 0u, 1.0f, n32);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) N[a] = R(n32[a]);
+    for (int a = 0; a < 6; ++a) D.n[a] = R(n32[a]);
   } else {
-    site_gaussians<R>(C.k0, C.k1, site, t, 0u, R(1), N);
+    site_gaussians<R>(C.k0, C.k1, site, t, 0u, R(1), D.n);
   }
 }
 
+// sqrt(rho) N: the Gaussians with the local-density factor of eq. (20).
+__device__ __forceinline__ void scaled_noise(const SiteDraw<float>& D, float rho, float N[6]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float r = sqrt_t(rho * D.l[k]);
+    N[2 * k] = r * D.cs[2 * k];
+    N[2 * k + 1] = r * D.cs[2 * k + 1];
+  }
+}
+__device__ __forceinline__ void scaled_noise(const SiteDraw<double>& D, double rho,
+                                             double N[6]) {
+  const double sr = rho * rsqrt_t(rho);
+#pragma unroll
+  for (int a = 0; a < 6; ++a) N[a] = D.n[a] * sr;
+}
+
 // One collision, eq. (6), on shifted populations h (in place), with the
-// site's unit Gaussians Nu (read only when the lattice has noise).  Returns
+// site's Gaussian draw (read only when the lattice has noise).  Returns
 // error bits; on error h is left unchanged.
 template <typename R, int BASIS>
-__device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C, const R Nu[6]) {
+__device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C,
+                                       const SiteDraw<R>& draw) {
   LocalState<R> S;
   if (!local_state(h, C.rho0, C.ux0, C.uy0, S)) return kErrNonFinite;
   const R ux = S.ux, uy = S.uy;
   const R* d = S.d;
 
-  // sqrt(rho) N: the local-density factor of the amplitudes of eq. (20)
   R N[6];
   if (C.noise) {
-    const R sr = S.rho * rsqrt_t(S.rho);
-#pragma unroll
-    for (int a = 0; a < 6; ++a) N[a] = Nu[a] * sr;
+    scaled_noise(draw, S.rho, N);
   } else {
 #pragma unroll
     for (int a = 0; a < 6; ++a) N[a] = R(0);
