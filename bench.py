@@ -176,6 +176,15 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                       sample_every=sample_every, block_steps=100 if sample_every > 0 else 0)
     L = F.Lattice(p, stream=stream)
     L.set_fields(*I.shear_wave_fields(nx, nx, ux0=ux0, amp=1e-3))
+    # the two bandwidth probes (the step's access pattern without arithmetic,
+    # and a plain contiguous copy of the same bytes) run first: they draw less
+    # power than the step and run at a higher clock, and the step kernels of
+    # the launch tuning and the warm-up that follow let the device's power
+    # control settle at the step's own clock before the timed steps
+    bps = BYTES_PER_SITE["f32" if fp32 else "f64"]
+    probes = {"copy_ms": F.copy_probe(nx, nx, F.FP32_SHIFTED if fp32 else F.FP64, reps=20),
+              "stream_bytes": bps // 2 * nx * nx}
+    probes["stream_ms"] = F.stream_copy_probe(probes["stream_bytes"], reps=20)
     if launch is None:
         tune = L.autotune(reps=3)  # trial steps run on a copy of the state
     else:
@@ -195,14 +204,6 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                 log.append(L.fourier_mode(2, 1, 0))
         return log
 
-    # the two bandwidth probes (the step's access pattern without arithmetic,
-    # and a plain contiguous copy of the same bytes) run before the timed
-    # steps: a second of full-bandwidth traffic also brings the device to its
-    # sustained clocks, which a few warm-up steps alone do not
-    bps = BYTES_PER_SITE["f32" if fp32 else "f64"]
-    probes = {"copy_ms": F.copy_probe(nx, nx, F.FP32_SHIFTED if fp32 else F.FP64, reps=20),
-              "stream_bytes": bps // 2 * nx * nx}
-    probes["stream_ms"] = F.stream_copy_probe(probes["stream_bytes"], reps=20)
     run(warmup)
     L.sync()
     torch.cuda.synchronize()
