@@ -177,10 +177,7 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
     L = F.Lattice(p, stream=stream)
     L.set_fields(*I.shear_wave_fields(nx, nx, ux0=ux0, amp=1e-3))
     # the two bandwidth probes (the step's access pattern without arithmetic,
-    # and a plain contiguous copy of the same bytes) run first: they draw less
-    # power than the step and run at a higher clock, and the step kernels of
-    # the launch tuning and the warm-up that follow let the device's power
-    # control settle at the step's own clock before the timed steps
+    # and a plain contiguous copy of the same bytes) run first
     bps = BYTES_PER_SITE["f32" if fp32 else "f64"]
     probes = {"copy_ms": F.copy_probe(nx, nx, F.FP32_SHIFTED if fp32 else F.FP64, reps=20),
               "stream_bytes": bps // 2 * nx * nx}
@@ -192,6 +189,20 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
         tune = "fixed by --launch"
 
     chunk = every if every > 0 else 100
+    # The step runs at the board's power limit (1400 W): after the lighter
+    # work above (the probes, and launch trials with host synchronisations
+    # between them) the shader clock needs tens of milliseconds of
+    # continuous steps to settle at the step's own level, longer than a few
+    # warm-up steps.  A second lattice of the same shape and launch shape
+    # steps for ~0.3 s right before the warm-up, in the same stream; it is
+    # untimed and shares nothing with the timed lattice, whose own warm-up is
+    # the W steps below.
+    settle = F.Lattice(F.make_params(nx, nx, precision=p.precision, basis=bcode, rho0=1.0,
+                                     ux0=ux0, kT=1e-4, seed=2, sample_every=sample_every,
+                                     block_steps=p.block_steps), stream=stream)
+    lc = L.get_launch()
+    settle.set_launch(lc["tiles_per_block"], lc["grid_blocks"])
+    settle_steps = max(20, int(round(300.0 / probes["copy_ms"])))
 
     def run(n):
         done = 0
@@ -204,9 +215,11 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                 log.append(L.fourier_mode(2, 1, 0))
         return log
 
+    settle.step(settle_steps)
     run(warmup)
     L.sync()
     torch.cuda.synchronize()
+    settle.close()
     L.profile(True)
     L.kernel_time()  # reset
     tw0 = L.t
@@ -238,7 +251,7 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                    "ms_per_step": round(dt1 * 1e3 / every, 4),
                    "mlups": round(sites * every / dt1 / 1e6, 1)}
     return {"sites": sites, "dt": dt, "kernel_ms": kms / max(launches, 1), "launches": launches,
-            "mode_log": [abs(z) for z in log[-3:]], "probes": probes,
+            "mode_log": [abs(z) for z in log[-3:]], "probes": probes, "settle_steps": settle_steps,
             "sk_in_window": n_sk, "mode_logs_in_window": len(log), "with_sk": with_sk,
             "launch": {"chosen": L.get_launch(), "candidates": tune},
             "config": {"workload": f"{nx}x{nx} D2Q9 {'FP32-shifted' if fp32 else 'FP64'}, "
@@ -546,7 +559,7 @@ def main():
                                      "what": "contiguous copy of the population bytes, "
                                              "16 B per thread"}},
         "pct_hbm_roofline": round(100 * mlups * 1e6 * bps / (HBM_PEAK_GBS * 1e9), 2),
-        "launch": r["launch"],
+        "launch": dict(r["launch"], settle_steps=r["settle_steps"]),
         "structure_factor": {"sk_every": args.sk_every, "sk_samples_in_window": r["sk_in_window"],
                              "mode_logs_in_window": r["mode_logs_in_window"],
                              "with_sk": r["with_sk"]},

@@ -509,62 +509,79 @@ __device__ __forceinline__ bool local_state(const R h[9], R rho0, R ux0, R uy0,
 // The Gaussian draw of one (site, step).  It needs only the site and the
 // step, so the step kernel makes it before the populations of the site have
 // arrived; the collision scales it by sqrt(rho), the local-density factor of
-// the amplitudes of eq. (20).  FP32 keeps the Box-Muller pieces (squared
-// radius, cosine, sine) and forms the radius there as sqrt(rho l), which
-// folds that factor into the square root it takes anyway.  FP64 keeps unit
-// Gaussians; NOISE32 draws them in FP32 although the collision runs in FP64
-// (FP32 storage above the FP32 basis speed: the stored result is rounded to
-// FP32 anyway, and the FP32 transform is a sixth of the FP64 one's cost).
-template <typename R>
+// the amplitudes of eq. (20).  The draw keeps the Box-Muller pieces (the
+// squared radius of unit variance l = -2 ln u, the cosine and the sine) and
+// the collision forms the radius as sqrt(rho l), which folds that factor
+// into the square root Box-Muller takes anyway.  NOISE32 (an FP64 collision
+// on FP32 storage above the FP32 basis speed) draws unit Gaussians in FP32
+// instead: the stored result is rounded to FP32 anyway, and the FP32
+// transform is a sixth of the FP64 one's cost.
+template <typename R, bool NOISE32>
 struct SiteDraw {
-  R n[6];  // unit Gaussians
+  R l[3];   // -2 ln u of each pair
+  R cs[6];  // cosine, sine of each pair's angle
 };
 template <>
-struct SiteDraw<float> {
-  float l[3];   // -2 ln u of each pair
-  float cs[6];  // cosine, sine of each pair's angle
+struct SiteDraw<double, true> {
+  double n[6];  // unit Gaussians, drawn in FP32
 };
+
+// The pieces of one FP64 pair (as box_muller_f64 without the radius).
+template <int BITS>
+__device__ __forceinline__ void box_muller_parts_f64(uint32_t ua, uint32_t ub, double& l,
+                                                     double& c, double& s) {
+  l = -2.0 * ln_uniform<BITS>(ua);
+  sincos_uniform<BITS>(ub, s, c);
+}
 
 template <typename R, bool NOISE32>
 __device__ __forceinline__ void site_draw(const CollideConst<R>& C, uint32_t site, uint64_t t,
-                                          SiteDraw<R>& D) {
-  if constexpr (sizeof(R) == 4) {
-    const Uniform21 u = site_uniforms(C.k0, C.k1, site, t, 0u);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      box_muller_parts_f32<21>(u.a[k], u.b[k], D.l[k], D.cs[2 * k], D.cs[2 * k + 1]);
-  } else if constexpr (NOISE32) {
+                                          SiteDraw<R, NOISE32>& D) {
+  if constexpr (NOISE32) {
     float n32[6];
     site_gaussians<float>(C.k0, C.k1, site, t, 0u, 1.0f, n32);
 #pragma unroll
     for (int a = 0; a < 6; ++a) D.n[a] = R(n32[a]);
   } else {
-    site_gaussians<R>(C.k0, C.k1, site, t, 0u, R(1), D.n);
+    const Uniform21 u = site_uniforms(C.k0, C.k1, site, t, 0u);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if constexpr (sizeof(R) == 4)
+        box_muller_parts_f32<21>(u.a[k], u.b[k], D.l[k], D.cs[2 * k], D.cs[2 * k + 1]);
+      else
+        box_muller_parts_f64<21>(u.a[k], u.b[k], D.l[k], D.cs[2 * k], D.cs[2 * k + 1]);
+    }
   }
 }
 
 // sqrt(rho) N: the Gaussians with the local-density factor of eq. (20).
-__device__ __forceinline__ void scaled_noise(const SiteDraw<float>& D, float rho, float N[6]) {
+template <typename R, bool NOISE32>
+__device__ __forceinline__ void scaled_noise(const SiteDraw<R, NOISE32>& D, R rho, R N[6]) {
+  if constexpr (NOISE32) {
+    const R sr = rho * rsqrt_t(rho);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float r = sqrt_t(rho * D.l[k]);
-    N[2 * k] = r * D.cs[2 * k];
-    N[2 * k + 1] = r * D.cs[2 * k + 1];
+    for (int a = 0; a < 6; ++a) N[a] = D.n[a] * sr;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const R a = rho * D.l[k];
+      R r;
+      if constexpr (sizeof(R) == 4)
+        r = sqrt_t(a);
+      else
+        r = a * rsqrt_t(a);  // a > 0: rho > 0 and u < 1
+      N[2 * k] = r * D.cs[2 * k];
+      N[2 * k + 1] = r * D.cs[2 * k + 1];
+    }
   }
-}
-__device__ __forceinline__ void scaled_noise(const SiteDraw<double>& D, double rho,
-                                             double N[6]) {
-  const double sr = rho * rsqrt_t(rho);
-#pragma unroll
-  for (int a = 0; a < 6; ++a) N[a] = D.n[a] * sr;
 }
 
 // One collision, eq. (6), on shifted populations h (in place), with the
 // site's Gaussian draw (read only when the lattice has noise).  Returns
 // error bits; on error h is left unchanged.
-template <typename R, int BASIS>
+template <typename R, int BASIS, bool NOISE32>
 __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C,
-                                       const SiteDraw<R>& draw) {
+                                       const SiteDraw<R, NOISE32>& draw) {
   LocalState<R> S;
   if (!local_state(h, C.rho0, C.ux0, C.uy0, S)) return kErrNonFinite;
   const R ux = S.ux, uy = S.uy;

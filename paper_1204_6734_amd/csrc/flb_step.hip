@@ -349,8 +349,9 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   const uint32_t site = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
   // the Gaussians need only the site and the step: drawn here, while the
   // loads are still in flight, they cover part of the load latency
-  SiteDraw<R> draw;  // read by the collision only where drawn
-  if (active && C.noise) site_draw<R, (sizeof(S) < sizeof(R))>(C, site, t, draw);
+  constexpr bool kNoise32 = sizeof(S) < sizeof(R);
+  SiteDraw<R, kNoise32> draw;  // read by the collision only where drawn
+  if (active && C.noise) site_draw<R, kNoise32>(C, site, t, draw);
 
   bool due = false;
   if (SAMPLE) {
@@ -374,7 +375,7 @@ __device__ __forceinline__ void step_tile(const SlotDesc* __restrict__ slots,
   }
 
   if (active) {
-    const int e = collide<R, BASIS>(h, C, draw);
+    const int e = collide<R, BASIS, kNoise32>(h, C, draw);
     if (e) {
       atomicOr(sd.err, e);
       atomicMin(sd.err_step, (unsigned long long)t);
