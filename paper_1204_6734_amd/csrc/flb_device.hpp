@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include "flb_kernels.hpp"
+#include "fp64_series.hpp"
 
 namespace flb {
 
@@ -129,15 +130,22 @@ __device__ __forceinline__ void box_muller<float, 24>(uint32_t ua, uint32_t ub, 
 // makes exact argument reduction cheap:
 // - ln x for x = (2 ua + 1) 2^-(B+1) in (0, 1): x = 2^e m with m in
 //   [sqrt(1/2), sqrt(2)), ln m = 2 artanh z with z = (m - 1)/(m + 1),
-//   |z| < 0.172, summed as the odd power series to z^21 (the rest is below
-//   2^-56 of the sum), and ln x = e ln 2 + ln m;
+//   |z| < 0.172, and ln x = e ln 2 + ln m;
 // - the angle theta = 2 pi (ub + 1/2) 2^-B = pi K 2^-B with K = 2 ub + 1:
 //   the octant is K >> (B - 2) and the rest an integer (taken from the
 //   octant's far end in odd octants), so the reduced angle r = pi k 2^-B in
-//   [0, pi/4] carries one rounding; sin r and cos r are their Taylor
-//   polynomials to r^17 and r^18 (the rest is below 1e-19);
+//   [0, pi/4] carries one rounding;
+// - artanh, sin and cos on those intervals are the economised series of
+//   fp64_series.hpp (truncation below 2^-57);
 // - the radius sqrt(a) = a rsqrt(a) with the refined reciprocal square root.
 // Each result is within a few ulp of the correctly rounded value.
+template <int N>
+__device__ __forceinline__ double horner(const double (&c)[N], double x) {
+  double p = c[N - 1];
+#pragma unroll
+  for (int k = N - 2; k >= 0; --k) p = fma(p, x, c[k]);
+  return p;
+}
 __device__ __forceinline__ double rsqrt_t(double x);
 __device__ __forceinline__ double rcp_t(double x);
 
@@ -150,18 +158,7 @@ __device__ __forceinline__ double ln_uniform(uint32_t ua) {
   const double m = low ? 2.0 * mant : mant;
   const int e = low ? ex - 1 : ex;
   const double z = (m - 1.0) * rcp_t(m + 1.0);
-  const double z2 = z * z;
-  double p = 1.0 / 21.0;
-  p = fma(p, z2, 1.0 / 19.0);
-  p = fma(p, z2, 1.0 / 17.0);
-  p = fma(p, z2, 1.0 / 15.0);
-  p = fma(p, z2, 1.0 / 13.0);
-  p = fma(p, z2, 1.0 / 11.0);
-  p = fma(p, z2, 1.0 / 9.0);
-  p = fma(p, z2, 1.0 / 7.0);
-  p = fma(p, z2, 1.0 / 5.0);
-  p = fma(p, z2, 1.0 / 3.0);
-  p = fma(p, z2, 1.0);
+  const double p = horner(kAtanhSeries, z * z);
   return fma((double)e, 0.69314718055994530942, 2.0 * z * p);
 }
 
@@ -174,26 +171,7 @@ __device__ __forceinline__ void sincos_uniform(uint32_t ub, double& sn, double& 
   const uint32_t k = odd ? (1u << (BITS - 2)) - rest : rest;
   const double r = (double)k * (3.14159265358979323846 / (double)(1u << BITS));
   const double r2 = r * r;
-  // factorials to 18! are exact in FP64, so each coefficient is one rounding
-  double ps = 1.0 / 355687428096000.0;           // 1/17!
-  ps = fma(ps, r2, -1.0 / 1307674368000.0);      // 1/15!
-  ps = fma(ps, r2, 1.0 / 6227020800.0);          // 1/13!
-  ps = fma(ps, r2, -1.0 / 39916800.0);           // 1/11!
-  ps = fma(ps, r2, 1.0 / 362880.0);              // 1/9!
-  ps = fma(ps, r2, -1.0 / 5040.0);               // 1/7!
-  ps = fma(ps, r2, 1.0 / 120.0);                 // 1/5!
-  ps = fma(ps, r2, -1.0 / 6.0);                  // 1/3!
-  ps = fma(ps, r2, 1.0);
-  double pc = -1.0 / 6402373705728000.0;         // 1/18!
-  pc = fma(pc, r2, 1.0 / 20922789888000.0);      // 1/16!
-  pc = fma(pc, r2, -1.0 / 87178291200.0);        // 1/14!
-  pc = fma(pc, r2, 1.0 / 479001600.0);           // 1/12!
-  pc = fma(pc, r2, -1.0 / 3628800.0);            // 1/10!
-  pc = fma(pc, r2, 1.0 / 40320.0);               // 1/8!
-  pc = fma(pc, r2, -1.0 / 720.0);                // 1/6!
-  pc = fma(pc, r2, 1.0 / 24.0);                  // 1/4!
-  pc = fma(pc, r2, -1.0 / 2.0);                  // 1/2!
-  pc = fma(pc, r2, 1.0);
+  const double ps = horner(kSinSeries, r2), pc = horner(kCosSeries, r2);
   // theta = Q pi/2 + a with a = r (even octant, Q = oct/2) or a = -r (odd
   // octant, Q = (oct + 1)/2 mod 4); (sin, cos)(Q pi/2 + a) =
   // (sin a, cos a), (cos a, -sin a), (-sin a, -cos a), (-cos a, sin a)
@@ -260,28 +238,28 @@ __device__ __forceinline__ void site_gaussians(uint32_t k0, uint32_t k1, uint32_
 }
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-// FP64 1/sqrt(x) and 1/x: the hardware estimates refined by Newton-Raphson
-// to within a few ulp of the correctly rounded values, at a fraction of the
-// cost of sqrt and divide.  The gfx950 estimates are good to 2^-24 relative
-// (measured on 4M arguments over [2^-20, 2^20]); a step squares the relative
-// error (times 1.5 for the square root), so two steps reach the FP64
-// rounding level for both.  Arguments are positive and finite here (pivots
-// and densities).
+// FP64 1/sqrt(x) and 1/x: the hardware estimates refined to within a few
+// ulp of the correctly rounded values, at a fraction of the cost of sqrt and
+// divide.  The gfx950 estimates r0 are good to 2^-24 relative (measured on
+// 4M arguments over [2^-20, 2^20]).  With e the residual (e = 1 - x r0^2,
+// resp. 1 - x r0), the exact values are r0 (1 - e)^(-1/2) = r0 (1 + e/2 +
+// 3e^2/8 + ...) and r0 / (1 - e) = r0 (1 + e + e^2 + ...); one correction
+// with the series to e^2 leaves a truncation of order e^3 ~ 2^-70, below
+// the rounding of the few FP64 operations that form it (one step of the
+// third-order method where two Newton steps took a few more operations).
+// Arguments are positive and finite here (pivots and densities).
 __device__ __forceinline__ double rsqrt_t(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-#pragma unroll
-  for (int k = 0; k < 2; ++k) r = fma(r, fma(-hx * r, r, 0.5), r);
-  return r;
+  const double r = __builtin_amdgcn_rsq(x);
+  const double e = fma(-(x * r), r, 1.0);
+  return fma(r, e * fma(e, 0.375, 0.5), r);
 }
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 __device__ __forceinline__ double rcp_t(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-#pragma unroll
-  for (int k = 0; k < 2; ++k) r = fma(r, fma(-x, r, 1.0), r);
-  return r;
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
 // Per-lattice constants of the collision, in the compute type.  The stored
