@@ -277,8 +277,10 @@ int flb_ensemble_kernel_time(flb_ensemble* E, double* ms, uint64_t* launches);
 void flb_ensemble_destroy(flb_ensemble* E);
 
 /* ------------------------------------------------------------ launch shape
- * The batched step works on 64 x 4 tiles of sites (one 64-lane wavefront per
- * tile row).  Its launch shape is a tuning choice that never changes a
+ * The batched step works on tiles of 256 sites, four 64-lane wavefronts:
+ * 256 x 1 (the four along one lattice row) on lattices at least 256 sites
+ * wide, 64 x 4 (one per tile row) on narrower ones.  Its launch shape is a
+ * tuning choice that never changes a
  * result: every shape computes bit-identical populations and correlator
  * sums (each tile forms its partial sums in the same order).
  *   tiles_per_block  tiles per workgroup: 1, 2 or 4 (256, 512, 1024 threads)
