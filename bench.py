@@ -483,8 +483,9 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
-                                   "decomposition is a design, not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the library steps a "
+                                   "lattice on one GPU (its multi-GPU decomposition is a design, "
+                                   "not implemented)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
