@@ -2,14 +2,19 @@
 """Benchmark of the fused fluctuating D2Q9 step (f-norm basis) on one GPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload large|ensemble|serve|paper|d3q19]
+                    [--workload large|ensemble|serve|paper|d3q19|config2|cpu]
 
 Default workload ("large"): one 8192 x 8192 periodic lattice, FP32 storage
 shifted by f^0(rho0, u0), rho0 = 1, u_x0 = 0.1, kT = 1e-4, all tau = 1, initial
 transverse shear wave u_y = 1e-3 sin(2 pi x / L).  One step is the whole
 hot path: the fused collide-and-stream kernel over all sites; every 100
 steps the structure factor of rho, j~_x, j~_y is sampled (2-D FFT) and the
-shear-mode amplitude j~_y(k = 2 pi / L) is read back.
+shear-mode amplitude j~_y(k = 2 pi / L) is read back.  Before the W warm-up
+steps the run measures two bandwidth probes (the step's loads and stores
+without arithmetic, and a contiguous copy of the same bytes), picks the
+launch shape (unless --launch fixes it) and steps a second lattice of the
+same shape for ~0.3 s, untimed, so that the timed steps start at the clock
+the board's power limit settles the step at.
 
 Prints one JSON line: MLUPS (lattice-site updates per second / 1e6) over
 the timed steps, the step kernel's achieved HBM bandwidth against the
@@ -54,6 +59,7 @@ FP32_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 # sources of the step kernel (the one whose HBM traffic the profiles record)
 KERNEL_SOURCES = ["paper_1204_6734_amd/csrc/flb_device.hpp",
+                  "paper_1204_6734_amd/csrc/fp64_series.hpp",
                   "paper_1204_6734_amd/csrc/flb_buffer.hpp",
                   "paper_1204_6734_amd/csrc/flb_step.hip",
                   "paper_1204_6734_amd/csrc/flb_kernels.hpp"]
