@@ -208,7 +208,7 @@ def run_large(F, torch, steps: int, warmup: int, nx: int = 8192, every: int = 10
                                      block_steps=p.block_steps), stream=stream)
     lc = L.get_launch()
     settle.set_launch(lc["tiles_per_block"], lc["grid_blocks"])
-    settle_steps = max(20, int(round(300.0 / probes["copy_ms"])))
+    settle_steps = min(20000, max(20, int(round(300.0 / probes["copy_ms"]))))
 
     def run(n):
         done = 0
