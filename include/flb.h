@@ -134,6 +134,16 @@ int flb_lattice_set_populations(flb_lattice* L, const double* f, uint64_t t);
  * handle's stream; device errors surface at the next sync/read. */
 int flb_lattice_step(flb_lattice* L, uint64_t nsteps);
 
+/* Graph chunk length: with steps > 0 (rounded up to an even number K),
+ * flb_lattice_step replays a captured hipGraph of K steps, with their
+ * correlator and structure-factor samples, at every time that is a multiple
+ * of K, and launches the rest eagerly; replays are used only when the
+ * sampling and structure-factor intervals divide K and never straddle the
+ * close of a time block.  Results are bit-identical to eager launches.  0
+ * (the default) launches every step eagerly.  FLB_E_ARG for steps outside
+ * 0..65536.  For small lattices, whose steps are bound by the launch rate. */
+int flb_lattice_set_graph_chunk(flb_lattice* L, int32_t steps);
+
 /* Wait for the stream; returns the first device error (FLB_E_INVALID_VELOCITY
  * or FLB_E_NONFINITE) raised since creation, with flb_lattice_error_step()
  * naming the step. */

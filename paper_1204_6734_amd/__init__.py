@@ -105,6 +105,7 @@ _SIGS = {
     "flb_lattice_set_fields": [C.c_void_p] + [C.POINTER(C.c_double)] * 3,
     "flb_lattice_set_populations": [C.c_void_p, C.POINTER(C.c_double), C.c_uint64],
     "flb_lattice_step": [C.c_void_p, C.c_uint64],
+    "flb_lattice_set_graph_chunk": [C.c_void_p, C.c_int32],
     "flb_lattice_sync": [C.c_void_p],
     "flb_lattice_read_populations": [C.c_void_p, C.POINTER(C.c_double)],
     "flb_lattice_read_rows": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)],
@@ -333,6 +334,11 @@ class Lattice(_Tunable):
 
     def step(self, n: int):
         _check(load().flb_lattice_step(self.h, n), "step")
+
+    def set_graph_chunk(self, steps: int):
+        """Replay captured hipGraphs of `steps` steps (0: launch eagerly);
+        results are unchanged (flb_lattice_set_graph_chunk)."""
+        _check(load().flb_lattice_set_graph_chunk(self.h, steps), "set_graph_chunk")
 
     def sync(self):
         _check(load().flb_lattice_sync(self.h), "sync")

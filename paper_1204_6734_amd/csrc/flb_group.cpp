@@ -244,12 +244,15 @@ bool Group::sk_due(int s, uint64_t tt) const {
 }
 
 // Work after the step kernel of time tt: structure-factor transform and
-// time-block bookkeeping.
-int Group::after_step(uint64_t tt) {
+// time-block bookkeeping.  After a graph replay the transforms of the
+// chunk's steps ran inside the graph (replayed = true): only the counts and
+// the time-block closes remain.
+int Group::after_step(uint64_t tt, bool replayed) {
   for (int s = 0; s < (int)P.size(); ++s) {
     if (sk_due(s, tt)) {
-      HIPC(launch_sk_sample(storage, d_z, d_zt, d_skacc, P[s].nx, P[s].ny, d_twx, d_twy, max_lds,
-                            st));
+      if (!replayed)
+        HIPC(launch_sk_sample(storage, d_z, d_zt, d_skacc, P[s].nx, P[s].ny, d_twx, d_twy,
+                              max_lds, st));
       nsk += 1;
     }
     if (sample_due(s, tt))
@@ -287,13 +290,15 @@ int Group::launch_one(uint32_t k, bool sample, int odd) {
 }
 
 // A captured chunk of graph_chunk steps can be replayed at every time that
-// is a multiple of graph_chunk when each slot's sampling interval divides the
-// chunk (the sampling pattern inside a chunk is then the same every time)
-// and no structure factors are taken.
+// is a multiple of graph_chunk when each slot's sampling and structure-factor
+// intervals divide the chunk: the pattern of sampled steps inside a chunk is
+// then the same every time.
 bool Group::graph_friendly() const {
-  if (d_skacc || graph_chunk <= 0) return false;
-  for (auto& p : P)
+  if (graph_chunk <= 0) return false;
+  for (auto& p : P) {
     if (p.sample_every > 0 && graph_chunk % p.sample_every != 0) return false;
+    if (d_skacc && p.sk_every > 0 && graph_chunk % p.sk_every != 0) return false;
+  }
   return true;
 }
 
@@ -317,10 +322,16 @@ int Group::capture_graph() {
   for (int k = 0; k < graph_chunk; ++k) {
     // replays start at multiples of graph_chunk (even), so step k of a chunk
     // has parity k & 1 and a slot samples there iff k is a multiple of its
-    // interval
+    // interval; a structure-factor step also takes the sampling variant (it
+    // writes the fields) and is followed by its transform
     bool sample = false;
-    for (auto& p : P) sample |= p.sample_every > 0 && k % p.sample_every == 0;
+    for (int s = 0; s < (int)P.size(); ++s)
+      sample |= sample_due(s, (uint64_t)k) || sk_due(s, (uint64_t)k);
     hipError_t e = launch_classes((uint32_t)k, sample, k & 1, launch);
+    for (int s = 0; s < (int)P.size() && e == hipSuccess; ++s)
+      if (sk_due(s, (uint64_t)k))
+        e = launch_sk_sample(storage, d_z, d_zt, d_skacc, P[s].nx, P[s].ny, d_twx, d_twy,
+                             max_lds, st);
     if (e != hipSuccess) {
       hipGraph_t g;
       (void)hipStreamEndCapture(st, &g);
@@ -357,7 +368,7 @@ int Group::step(uint64_t nsteps) {
         HIPC(hipGraphLaunch(graph_exec, st));
       }
       for (uint64_t k = 0; k < K; ++k) {
-        rc = after_step(t + k);
+        rc = after_step(t + k, true);
         if (rc != FLB_OK) return rc;
       }
       t += K;
@@ -737,6 +748,15 @@ int flb_lattice_set_populations(flb_lattice* L, const double* f, uint64_t t) {
   NEED(L);
   if (!f) return flb::set_error(FLB_E_ARG, "null populations");
   return L->g.set_populations(0, f, t);
+}
+int flb_lattice_set_graph_chunk(flb_lattice* L, int32_t steps) {
+  NEED(L);
+  if (steps < 0 || steps > (1 << 16)) return flb::set_error(FLB_E_ARG, "bad chunk %d", steps);
+  const hipError_t e = hipStreamSynchronize(L->g.st);  // no replay in flight
+  if (e != hipSuccess) return flb::hip_fail(e, "sync");
+  L->g.drop_graph();
+  L->g.graph_chunk = steps + (steps & 1);  // even: replays keep the streaming phase
+  return FLB_OK;
 }
 int flb_lattice_step(flb_lattice* L, uint64_t n) {
   NEED(L);

@@ -80,7 +80,7 @@ struct Group {
   int init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t dev_bytes);
   bool sample_due(int s, uint64_t tt) const;
   bool sk_due(int s, uint64_t tt) const;
-  int after_step(uint64_t tt);
+  int after_step(uint64_t tt, bool replayed = false);
   int launch_one(uint32_t k, bool sample, int odd);
   hipError_t launch_classes(uint32_t k, bool sample, int odd, LaunchCfg c);
   bool graph_friendly() const;

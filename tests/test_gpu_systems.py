@@ -46,6 +46,48 @@ def test_ensemble_graph_replay_equals_eager(flb):
             np.testing.assert_array_equal(a.covariance(i)["cov_f"], b.covariance(i)["cov_f"])
 
 
+@pytest.mark.parametrize("prec,nx,ny", [("fp64", 96, 40), ("fp32", 96, 40), ("fp32", 32, 32)])
+def test_lattice_graph_replay_equals_eager(flb, prec, nx, ny):
+    """A lattice replaying captured graphs of 20 steps, with the correlator
+    samples of every step and a structure-factor transform every 10 steps
+    inside them, against the same lattice launched eagerly: populations,
+    correlator sums, time blocks (closing every 30 samples, which replays
+    may not straddle) and structure factors are bit-identical after every
+    call of a schedule of odd lengths (eager steps up to the next multiple
+    of 20, replays, eager remainders), with host synchronisations between
+    the replays, and again after a statistics reset."""
+    precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+    kw = dict(precision=precision, ux0=0.1, kT=1e-4, tau=I.mixed_taus(2), seed=5,
+              sample_every=1, sk_every=10, block_steps=30)
+    a = flb.Lattice(flb.make_params(nx, ny, **kw))
+    b = flb.Lattice(flb.make_params(nx, ny, **kw))
+    b.set_graph_chunk(20)
+
+    def same():
+        a.sync()
+        b.sync()
+        np.testing.assert_array_equal(a.populations(), b.populations())
+        ca, cb = a.covariance(), b.covariance()
+        for k, v in ca.items():
+            np.testing.assert_array_equal(v, cb[k], err_msg=k)
+        for w in range(5):
+            np.testing.assert_array_equal(a.structure_factor(w), b.structure_factor(w))
+
+    for n in (7, 33, 40, 1, 59, 20, 20):
+        a.step(n)
+        b.step(n)
+        same()
+    a.reset_stats()
+    b.reset_stats()
+    for n in (3, 77):
+        a.step(n)
+        b.step(n)
+        same()
+    assert a.covariance()["nsamples"] == 80 * nx * ny
+    a.close()
+    b.close()
+
+
 def _serve(F, reqs, budget, slots=8, chunk=50):
     S = F.Server(budget, max_slots=slots, chunk_steps=chunk, threaded=False)
     ids = {}
