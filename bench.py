@@ -44,13 +44,13 @@ BYTES_PER_SITE = {"f32": 72, "f64": 144}
 # D3Q19 FP32 f-norm step: VALU wavefront instructions per wavefront (= per
 # site), SQ_INSTS_VALU / SQ_WAVES averaged over both phases,
 # profiles/step3_fp32_256cube_d3q19.md
-D3Q19_VALU_PER_SITE = 2526
+D3Q19_VALU_PER_SITE = 2297
 # FP32 floating-point operations per site of that kernel, counted in its
-# gfx950 code: FMAs 2 each (1640 v_fma/v_fmac/v_fmamk), multiplies, adds and
-# subtracts 1 each (338 + 229), transcendentals (rsq, rcp, sqrt, log, sin,
-# cos) 1 each (50); conversions, compares and min/max are not counted.  One
+# gfx950 code: FMAs 2 each (1624 v_fma/v_fmac/v_fmamk), multiplies, adds and
+# subtracts 1 each (254 + 85), transcendentals (rsq, rcp, sqrt, log, sin,
+# cos) 1 each (48); conversions, compares and min/max are not counted.  One
 # lane computes one site.
-D3Q19_FLOPS_PER_SITE = 3897
+D3Q19_FLOPS_PER_SITE = 3635
 # FP32 vector peak without packed (two-wide) instructions, which this
 # library does not use: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9

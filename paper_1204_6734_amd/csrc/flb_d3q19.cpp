@@ -114,10 +114,8 @@ struct Lattice3 {
     for (int a = 0; a < 15; ++a) {
       h.rt[a] = 1.0 / p.tau[a];
       h.xc[a] = std::sqrt(mu * (2 * p.tau[a] - 1)) / p.tau[a];
-      h.keep[a] = 1.0 - h.rt[a];
       h.rtf[a] = (float)h.rt[a];
       h.xcf[a] = (float)h.xc[a];
-      h.keepf[a] = (float)h.keep[a];
     }
     for (int i = 0; i < 19; ++i) h.shift[i] = equilibrium3(i, p.rho0, h.u0);
     // one allocation: descriptor, clock, error flags, populations, partials,

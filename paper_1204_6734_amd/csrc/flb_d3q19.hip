@@ -28,7 +28,7 @@ constexpr double kS3 = 1.7320508075688772935;
 template <typename R>
 struct Const3 {
   R rho0, u0[3];
-  R rt[15], xc[15], keep[15];  // 1/tau, xi / sqrt(rho), 1 - 1/tau
+  R rt[15], xc[15];  // 1/tau, xi / sqrt(rho)
 };
 
 template <typename R>
@@ -41,7 +41,6 @@ __device__ __forceinline__ Const3<float> const3<float>(const Desc3& d) {
   for (int a = 0; a < 15; ++a) {
     c.rt[a] = d.rtf[a];
     c.xc[a] = d.xcf[a];
-    c.keep[a] = d.keepf[a];
   }
   return c;
 }
@@ -53,7 +52,6 @@ __device__ __forceinline__ Const3<double> const3<double>(const Desc3& d) {
   for (int a = 0; a < 15; ++a) {
     c.rt[a] = d.rt[a];
     c.xc[a] = d.xc[a];
-    c.keep[a] = d.keep[a];
   }
   return c;
 }
@@ -242,29 +240,23 @@ __device__ __forceinline__ int collide3_hermite(R h[19], const Const3<R>& C, int
 }
 
 constexpr int kBlock3 = 256;   // threads per workgroup (one 64 x 4 tile)
-constexpr int kParkRows = 8;   // rows 1..8 of the Cholesky factor kept in LDS
-constexpr int kPark = kParkRows * (kParkRows + 1) / 2;  // values per thread
-
-// The f-norm collision (BASIS 0) arranged for few live registers, so that
-// two wavefronts share a SIMD: the post-collision state is rebuilt from the
-// basis expansion of eqs. (17)-(18) and (32) instead of being added to the
-// loaded one,
-//   f*_i = rho g_i + sum_{a >= 4} n~^a_i M~*^a,  M~*^a = (1 - 1/tau^a) M~^a + xi^a N^a,
-// (the momentum modes sqrt3 (v - u) have zero moments), so neither h nor g
-// nor the projections P stay live across the factorisation.  The Gaussians
-// are drawn first and consumed column by column; the Schur complement is
-// formed one column at a time inside the Cholesky sweep, which also takes
-// the forward solve in column form; rows of the factor that only the back
-// substitution still needs wait in LDS (`park`, this thread's slot of a
-// [kPark][kBlock3] array).  In shifted variables, rho g_i - f_i^0(rho0, u0)
-// = drho g_i + rho0 (g_i(u) - g_i(u0)), the second difference formed from
-// du.  Returns error bits; hout is written only on success (on failure the
-// caller reads the site's values again, so nothing of the input has to stay
-// live for the failing lanes while the others go on).
+// The f-norm collision (BASIS 0).  The change of the populations is
+// df = sum_{a >= 4} n~^a dM~^a with n~^a = m~^a g and dM~^a = -M~^a / tau^a +
+// xi^a N^a (eqs. (6), (20)): a g-weighted combination of the rows 4..18
+// projected off the conserved ones 1, sqrt3 (v_a - u_a).  Its conserved
+// moments vanish, and its moments on rows 4..18 are G' y = L dM~ (G' = L L^T
+// the Schur complement of the Gram matrix, y = L^-T dM~ the coefficients of
+// the projected rows).  The rows are orthonormal under the weights w, so
+// df_i = w_i sum_b m^b_i (L dM~)_b, the back-transform of the Hermite-type
+// collision.  L dM~ is accumulated column by column inside the Cholesky
+// sweep, which also forms the Schur complement one column at a time and
+// takes the forward solve M~ = L^-1 d in column form, so each row of the
+// factor is dropped as soon as its column is done.  Returns error bits; hout
+// is written only on success (on failure the caller reads the site's values
+// again).
 template <typename R>
 __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C, int noise,
-                                              const R Nu[15], R* __restrict__ park,
-                                              R hout[19]) {
+                                              const R Nu[15], R hout[19]) {
   R M[19];
   moments3(h, M);
   const R drho = M[0];
@@ -280,18 +272,16 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
   const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   // g of a velocity pair (c, -c) is w (t +- 3 c.u); the smaller is w (t - |3 c.u|)
   const R base = R(1) - R(1.5) * uu;
-  R gmin = R(kW3[0]) * base;
+  R gmin = base;
 #pragma unroll
   for (int k = 1; k < 19; k += 2) {
     const R cu = cdot<R>(k, u);
-    gmin = fmin(gmin, R(kW3[k]) * ((base + R(4.5) * cu * cu) - fabs(R(3) * cu)));
+    gmin = fmin(gmin, (base + R(4.5) * cu * cu) - fabs(R(3) * cu));
   }
   if (!(rho > R(0)) || !(du[0] == du[0]) || !(du[1] == du[1]) || !(du[2] == du[2]))
     return kErrNonFinite;
   if (!(gmin > R(0))) return kErrInvalidVelocity;
-  const int err = 0;
 
-  // the scaled Gaussians first: they are consumed column by column below
   R N[15];
   scaled_noise(noise, rho, Nu, N);
 
@@ -323,12 +313,12 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
       P[a][b - 4] = ga - R(kS3) * u[a] * pi;
     }
   }
-  // Cholesky factor of the Schur complement G' = <m^a, m^b>_g - P0 P0^T -
-  // sum_a P_a P_a^T (packed lower part L[i(i+1)/2 + j], inverse pivots r),
-  // one column at a time; each column also takes its step of the forward
-  // solve M~ = L^-1 d in column form (d_i -= L_ij M~_j for i > j), after
-  // which M~_j is relaxed at once: x_j = M~*_j = (1 - 1/tau_j) M~_j + xi_j N_j
-  R L[120], r[15], x[15];
+  // Column j: the column of G' = <m^a, m^b>_g - P0 P0^T - sum_a P_a P_a^T
+  // less the columns of L before it (packed lower part L[i(i+1)/2 + k]), the
+  // pivot q and its inverse square root r, the column of L, the forward-solve
+  // step (M~_j = d_j r, then d_i -= L_ij M~_j for i > j), the relaxation
+  // dM~_j, and its contribution L_ij dM~_j to Y_i for i >= j (L_jj = q r).
+  R L[120], Y[15];
 #pragma unroll
   for (int j = 0; j < 15; ++j) {
 #pragma unroll
@@ -344,71 +334,25 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
       for (int k = 0; k < j; ++k) G -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
       L[i * (i + 1) / 2 + j] = G;
     }
-    r[j] = rsqrt_t(L[j * (j + 1) / 2 + j]);
-    const R mj = d[j] * r[j];
+    const R q = L[j * (j + 1) / 2 + j];
+    const R r = rsqrt_t(q);
+    const R mj = d[j] * r;
 #pragma unroll
     for (int i = j + 1; i < 15; ++i) {
-      L[i * (i + 1) / 2 + j] *= r[j];
+      L[i * (i + 1) / 2 + j] *= r;
       d[i] -= L[i * (i + 1) / 2 + j] * mj;
     }
-    x[j] = C.keep[j] * mj + C.xc[j] * N[j];
-    // row j is now needed only by the back substitution: rows 1..kParkRows
-    // wait for it in LDS (one value per thread, stride one workgroup)
-    if (j >= 1 && j <= kParkRows) {
+    const R D = C.xc[j] * N[j] - C.rt[j] * mj;
+    Y[j] = j == 0 ? (q * r) * D : Y[j] + (q * r) * D;
 #pragma unroll
-      for (int k = 0; k < j; ++k) park[(j * (j - 1) / 2 + k) * kBlock3] = L[j * (j + 1) / 2 + k];
-    }
+    for (int i = j + 1; i < 15; ++i)
+      Y[i] = j == 0 ? L[i * (i + 1) / 2 + j] * D : Y[i] + L[i * (i + 1) / 2 + j] * D;
   }
-  asm volatile("" ::: "memory");  // the parked rows are read back from LDS
-  // y = L^-T M~*, by rows of L from the last (x_i -= L_ki y_k for i < k)
-  R y[15];
+  R sg[19];
+  back3(Y, sg);
 #pragma unroll
-  for (int k = 14; k >= 0; --k) {
-    y[k] = x[k] * r[k];
-#pragma unroll
-    for (int i = 0; i < k; ++i) {
-      const R l = k <= kParkRows ? park[(k * (k - 1) / 2 + i) * kBlock3] : L[k * (k + 1) / 2 + i];
-      x[i] -= l * y[k];
-    }
-  }
-  // sum_a n~^a_i M~*^a = g_i [sigma_i - A0 - sum_a m~^a_i A_a] with
-  // sigma_i = sum_b m^b_i y_b, A0 = <1, sigma>_g, A_a = <m~^a, sigma>_g, and
-  // m~^a_i = sqrt3 (c_ia - u_a): = g_i [sigma_i + K - sum_a c_ia B_a]
-  R sg[19], g[19];
-  back3(y, sg);
-  g[0] = R(kW3[0]) * base;
-  R A0 = g[0] * sg[0], Cg[3] = {R(0), R(0), R(0)};
-#pragma unroll
-  for (int k = 1; k < 19; k += 2) {
-    const R cu = cdot<R>(k, u);
-    const R t = R(kW3[k]) * (base + R(4.5) * cu * cu), d = R(3 * kW3[k]) * cu;
-    g[k] = t + d;
-    g[k + 1] = t - d;
-    const R gp = g[k] * sg[k], gm = g[k + 1] * sg[k + 1];
-    A0 += gp + gm;
-    const R dl = gp - gm;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (kC3[k][a] > 0) Cg[a] += dl;
-      if (kC3[k][a] < 0) Cg[a] -= dl;
-    }
-  }
-  R B[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) B[a] = R(3) * (Cg[a] - u[a] * A0);
-  const R K = u[0] * B[0] + u[1] * B[1] + u[2] * B[2] - A0 + drho;
-  const R dusu = du[0] * su[0] + du[1] * su[1] + du[2] * su[2];
-  // g_i(u) - g_i(u0) = w_i (3 c.du + 4.5 (c.du)(c.su) - 1.5 du.su): the
-  // first term flips sign between c and -c, the rest does not
-  hout[0] = g[0] * (sg[0] + K) + C.rho0 * (R(kW3[0]) * (R(-1.5) * dusu));
-#pragma unroll
-  for (int k = 1; k < 19; k += 2) {
-    const R cB = cdot<R>(k, B), cdu = cdot<R>(k, du), csu = cdot<R>(k, su);
-    const R e = R(kW3[k]) * (R(4.5) * cdu * csu - R(1.5) * dusu), dd = R(3 * kW3[k]) * cdu;
-    hout[k] = g[k] * ((sg[k] + K) - cB) + C.rho0 * (e + dd);
-    hout[k + 1] = g[k + 1] * ((sg[k + 1] + K) + cB) + C.rho0 * (e - dd);
-  }
-  return err;
+  for (int i = 0; i < 19; ++i) hout[i] = h[i] + R(kW3[i]) * sg[i];
+  return 0;
 }
 
 // --------------------------------------------------------------- kernels
@@ -484,11 +428,11 @@ __device__ __forceinline__ uint32_t cell(int x, int y, int z, const Desc3& d) {
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 // Wavefronts per SIMD the register allocation of a step variant aims at:
-// two in FP32 (at three the f-norm collision spills; measured no faster),
-// one in FP64.
+// three in FP32 (the f-norm collision then spills 32-40 bytes per lane and
+// still runs 1.5 % faster than at two), one in FP64.
 template <typename R>
 constexpr int waves3() {
-  return sizeof(R) == 8 ? 1 : 2;
+  return sizeof(R) == 8 ? 1 : 3;
 }
 
 // One 64 x 4 tile of one z plane per workgroup, one wavefront per tile row,
@@ -498,7 +442,7 @@ constexpr int waves3() {
 // row part (nine distinct (y, z) shifts) is scalar.  Tiles are renumbered
 // so that each XCD sweeps a contiguous range of z planes.
 template <typename S, typename R, int BASIS, bool SAMPLE, int ODD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves3<R>()))) void
+__global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(waves3<R>()))) void
 step3_kernel(const Desc3* __restrict__ desc, const uint64_t* __restrict__ clock,
              uint32_t step_idx) {
   const Desc3& d = *desc;
@@ -550,11 +494,10 @@ step3_kernel(const Desc3* __restrict__ desc, const uint64_t* __restrict__ clock,
   }
   if (!active) return;
   const Const3<R> C = const3<R>(d);
-  __shared__ R park[BASIS == 0 ? kPark : 1][kBlock3];
   R hn[19];
   int e;
   if constexpr (BASIS == 0) {
-    e = collide3_fnorm<R>(h, C, d.noise, Nu, &park[0][threadIdx.x], hn);
+    e = collide3_fnorm<R>(h, C, d.noise, Nu, hn);
   } else {
     e = collide3_hermite<R, !kEarlyNoise>(h, C, d.noise, Nu, d.k0, d.k1, cell(x, y, z, d), t);
 #pragma unroll
@@ -635,7 +578,7 @@ __global__ void fill3_kernel(double* p, size_t n) {
 template <typename S, typename R, int BASIS>
 static hipError_t step3_t(bool sample, int odd, int ntiles, const Desc3* d,
                           const uint64_t* clock, uint32_t k, hipStream_t st) {
-  const dim3 g(ntiles), b(256);
+  const dim3 g(ntiles), b(kBlock3);
   if (sample) {
     if (odd)
       hipLaunchKernelGGL((step3_kernel<S, R, BASIS, true, 1>), g, b, 0, st, d, clock, k);

@@ -20,9 +20,8 @@ struct Desc3 {
   int sample_every, noise;
   double rho0, u0[3];
   double rt[15], xc[15];         // 1/tau, sqrt(mu (2 tau - 1)) / tau
-  double keep[15];               // 1 - 1/tau
   double shift[19];              // f_i^0(rho0, u0)
-  float rho0f, u0f[3], rtf[15], xcf[15], keepf[15];  // the same in FP32
+  float rho0f, u0f[3], rtf[15], xcf[15];  // the same in FP32
 };
 
 hipError_t launch_step3(int storage, int basis, bool sample, int odd, int ntiles, const Desc3* d,

@@ -350,15 +350,32 @@ __device__ __forceinline__ void unit_equilibrium(R bx, R by, R g[9]) {
   g[8] = R(1.0 / 36.0) * (d6 - R(3) * c6);
 }
 
-// Local f-norm factors at basis velocity (bx, by): inverse pivots r[6] and
-// strict lower part of the Cholesky factor of the Schur complement, plus the
-// conserved-row projections P0, P1, P2 of Hermite rows 3..7 (row 8 has none).
+// Whether every g_i = f_i^0(1, u) of eq. (A1) is positive.  The weights are
+// positive, so each sign is that of the bracket; the pair of opposite
+// velocities +-c shares the bracket's even part e and has the smaller value
+// e - 3 |u.c| (the same number as min(e + 3 u.c, e - 3 u.c) in any rounding).
+template <typename R>
+__device__ __forceinline__ bool valid_velocity(R bx, R by) {
+  const R xx = bx * bx, yy = by * by;
+  const R base = R(1) - R(1.5) * (xx + yy);
+  const R c5 = bx + by, c6 = by - bx;
+  const R ax = (base + R(4.5) * xx) - R(3) * fabs(bx);
+  const R ay = (base + R(4.5) * yy) - R(3) * fabs(by);
+  const R d5 = (base + R(4.5) * c5 * c5) - R(3) * fabs(c5);
+  const R d6 = (base + R(4.5) * c6 * c6) - R(3) * fabs(c6);
+  return fmin(fmin(base, fmin(ax, ay)), fmin(d5, d6)) > R(0);
+}
+
+// Local f-norm factors at basis velocity (bx, by): the Cholesky factor L of
+// the Schur complement G' of the Hermite rows 3..8 under <,>_g (the Gram
+// matrix with the projections on the conserved rows 1, m~^1, m~^2 taken out;
+// Gram-Schmidt of eq. (11) in that order is the same factorisation), as its
+// inverse pivots r[6], its diagonal and its strict lower part.
 template <typename R>
 struct Basis {
   R r[6];
+  R dg[6];  // diagonal of the factor, sqrt(pivot) = pivot r
   R L[15];  // L10 L20 L21 L30 L31 L32 L40 L41 L42 L43 L50 L51 L52 L53 L54
-  R P0[3];            // rows 3,4,5
-  R P1[5], P2[5];     // rows 3..7
 };
 
 template <typename R>
@@ -369,19 +386,17 @@ __device__ __forceinline__ void fnorm_basis(R bx, R by, Basis<R>& B) {
   const R xx = bx * bx, yy = by * by, xy = bx * by, uu = xx + yy, dd = xx - yy;
   // conserved-row projections <1, m^a>_g, <m~^1, m^a>_g, <m~^2, m^a>_g
   const R P03 = R(1.5) * dd, P04 = R(3) * xy, P05 = R(1.5) * uu;
-  B.P0[0] = P03; B.P0[1] = P04; B.P0[2] = P05;
-  B.P1[0] = S3 * bx * (R(1) - P03);
-  B.P1[1] = S3 * by * (R(1) - R(3) * xx);
-  B.P1[2] = S3 * bx * (R(1) - P05);
-  B.P1[3] = T2 * yy;
-  B.P1[4] = R(2) * T2 * xy;
-  B.P2[0] = -S3 * by * (R(1) + P03);
-  B.P2[1] = S3 * bx * (R(1) - R(3) * yy);
-  B.P2[2] = S3 * by * (R(1) - P05);
-  B.P2[3] = R(2) * T2 * xy;
-  B.P2[4] = T2 * xx;
-  const R* p1 = B.P1;
-  const R* p2 = B.P2;
+  R p1[5], p2[5];  // rows 3..7 (row 8 has none)
+  p1[0] = S3 * bx * (R(1) - P03);
+  p1[1] = S3 * by * (R(1) - R(3) * xx);
+  p1[2] = S3 * bx * (R(1) - P05);
+  p1[3] = T2 * yy;
+  p1[4] = R(2) * T2 * xy;
+  p2[0] = -S3 * by * (R(1) + P03);
+  p2[1] = S3 * bx * (R(1) - R(3) * yy);
+  p2[2] = S3 * by * (R(1) - P05);
+  p2[3] = R(2) * T2 * xy;
+  p2[4] = T2 * xx;
   // Hermite Gram matrix under g minus the conserved projections (lower part).
   const R A00 = (R(1) + R(0.75) * uu) - (P03 * P03 + p1[0] * p1[0] + p2[0] * p2[0]);
   const R A10 = -(P04 * P03 + p1[1] * p1[0] + p2[1] * p2[0]);
@@ -402,25 +417,33 @@ __device__ __forceinline__ void fnorm_basis(R bx, R by, Basis<R>& B) {
   const R A53 = S6 * bx, A54 = S6 * by, A55 = R(1) + R(1.5) * uu;
   // Cholesky, columns in Gram-Schmidt order.
   R* L = B.L;
-  const R r0 = rsqrt_t(A00);
+  const R q0 = A00;
+  const R r0 = rsqrt_t(q0);
   L[0] = A10 * r0; L[1] = A20 * r0; L[3] = A30 * r0; L[6] = A40 * r0; L[10] = A50 * r0;
-  const R r1 = rsqrt_t(A11 - L[0] * L[0]);
+  const R q1 = A11 - L[0] * L[0];
+  const R r1 = rsqrt_t(q1);
   L[2] = (A21 - L[1] * L[0]) * r1;
   L[4] = (A31 - L[3] * L[0]) * r1;
   L[7] = (A41 - L[6] * L[0]) * r1;
   L[11] = (A51 - L[10] * L[0]) * r1;
-  const R r2 = rsqrt_t(A22 - L[1] * L[1] - L[2] * L[2]);
+  const R q2 = A22 - L[1] * L[1] - L[2] * L[2];
+  const R r2 = rsqrt_t(q2);
   L[5] = (A32 - L[3] * L[1] - L[4] * L[2]) * r2;
   L[8] = (A42 - L[6] * L[1] - L[7] * L[2]) * r2;
   L[12] = (A52 - L[10] * L[1] - L[11] * L[2]) * r2;
-  const R r3 = rsqrt_t(A33 - L[3] * L[3] - L[4] * L[4] - L[5] * L[5]);
+  const R q3 = A33 - L[3] * L[3] - L[4] * L[4] - L[5] * L[5];
+  const R r3 = rsqrt_t(q3);
   L[9] = (A43 - L[6] * L[3] - L[7] * L[4] - L[8] * L[5]) * r3;
   L[13] = (A53 - L[10] * L[3] - L[11] * L[4] - L[12] * L[5]) * r3;
-  const R r4 = rsqrt_t(A44 - L[6] * L[6] - L[7] * L[7] - L[8] * L[8] - L[9] * L[9]);
+  const R q4 = A44 - L[6] * L[6] - L[7] * L[7] - L[8] * L[8] - L[9] * L[9];
+  const R r4 = rsqrt_t(q4);
   L[14] = (A54 - L[10] * L[6] - L[11] * L[7] - L[12] * L[8] - L[13] * L[9]) * r4;
-  const R r5 = rsqrt_t(A55 - L[10] * L[10] - L[11] * L[11] - L[12] * L[12] - L[13] * L[13] -
-                       L[14] * L[14]);
+  const R q5 = A55 - L[10] * L[10] - L[11] * L[11] - L[12] * L[12] - L[13] * L[13] -
+               L[14] * L[14];
+  const R r5 = rsqrt_t(q5);
   B.r[0] = r0; B.r[1] = r1; B.r[2] = r2; B.r[3] = r3; B.r[4] = r4; B.r[5] = r5;
+  B.dg[0] = q0 * r0; B.dg[1] = q1 * r1; B.dg[2] = q2 * r2;
+  B.dg[3] = q3 * r3; B.dg[4] = q4 * r4; B.dg[5] = q5 * r5;
 }
 
 // Forward substitution x = L^-1 d.
@@ -436,17 +459,17 @@ __device__ __forceinline__ void lower_solve(const Basis<R>& B, const R d[6], R x
          B.r[5];
 }
 
-// Back substitution y = L^-T v.
+// Product y = L v with the full factor (diagonal included).
 template <typename R>
-__device__ __forceinline__ void upper_solve(const Basis<R>& B, const R v[6], R y[6]) {
+__device__ __forceinline__ void lower_mul(const Basis<R>& B, const R v[6], R y[6]) {
   const R* L = B.L;
-  y[5] = v[5] * B.r[5];
-  y[4] = (v[4] - L[14] * y[5]) * B.r[4];
-  y[3] = (v[3] - L[9] * y[4] - L[13] * y[5]) * B.r[3];
-  y[2] = (v[2] - L[5] * y[3] - L[8] * y[4] - L[12] * y[5]) * B.r[2];
-  y[1] = (v[1] - L[2] * y[2] - L[4] * y[3] - L[7] * y[4] - L[11] * y[5]) * B.r[1];
-  y[0] = (v[0] - L[0] * y[1] - L[1] * y[2] - L[3] * y[3] - L[6] * y[4] - L[10] * y[5]) *
-         B.r[0];
+  y[0] = B.dg[0] * v[0];
+  y[1] = B.dg[1] * v[1] + L[0] * v[0];
+  y[2] = B.dg[2] * v[2] + L[1] * v[0] + L[2] * v[1];
+  y[3] = B.dg[3] * v[3] + L[3] * v[0] + L[4] * v[1] + L[5] * v[2];
+  y[4] = B.dg[4] * v[4] + L[6] * v[0] + L[7] * v[1] + L[8] * v[2] + L[9] * v[3];
+  y[5] = B.dg[5] * v[5] + L[10] * v[0] + L[11] * v[1] + L[12] * v[2] + L[13] * v[3] +
+         L[14] * v[4];
 }
 
 // Local state of a site from its shifted populations: rho, u, u - u0 and the
@@ -573,67 +596,46 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C,
     for (int a = 0; a < 6; ++a) N[a] = R(0);
   }
 
+  // Hermite moments Y of the change of the populations, rows 3..8 (its
+  // conserved moments vanish).
+  R Y[6];
   if (BASIS == kBasisHermite) {
     // App. A: n = w m, relaxation of M - M^0 with the same amplitudes.
-    R Y[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) Y[a] = C.xc[a] * N[a] - C.rt[a] * d[a];
-    R s[9];
-    hermite_back(Y, s);
-    constexpr R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
-    h[0] += w0 * s[0];
+  } else {
+    R bx = ux, by = uy;
+    if (BASIS == kBasisFnormLut) {
+      // nearest point of the 51 x 51 grid, spacing 0.02, [-0.5, 0.5]^2
+      const R fx = floor(ux / R(0.02) + R(0.5)), fy = floor(uy / R(0.02) + R(0.5));
+      if (!(fabs(fx) <= R(25) && fabs(fy) <= R(25))) return kErrInvalidVelocity;
+      bx = fx * R(0.02);
+      by = fy * R(0.02);
+    }
+    if (!valid_velocity(bx, by)) return kErrInvalidVelocity;
+    // The change is df = sum_a n~^a dM~^a with n~^a = m~^a g (eq. (6)), a
+    // g-weighted combination of the rows projected off the conserved ones.
+    // Its conserved Hermite moments therefore vanish, and rows 3..8 give
+    // G' y = L dM~ (G' = L L^T the Schur complement, y = L^-T dM~ the
+    // coefficients of the projected rows).
+    Basis<R> B;
+    fnorm_basis(bx, by, B);
+    R Mt[6], D[6];
+    lower_solve(B, d, Mt);  // non-equilibrium f-norm moments M~^{3..8}
 #pragma unroll
-    for (int i = 1; i < 5; ++i) h[i] += w1 * s[i];
-#pragma unroll
-    for (int i = 5; i < 9; ++i) h[i] += w5 * s[i];
-    return 0;
+    for (int a = 0; a < 6; ++a) D[a] = C.xc[a] * N[a] - C.rt[a] * Mt[a];
+    lower_mul(B, D, Y);
   }
-
-  R bx = ux, by = uy;
-  if (BASIS == kBasisFnormLut) {
-    // nearest point of the 51 x 51 grid, spacing 0.02, [-0.5, 0.5]^2
-    const R fx = floor(ux / R(0.02) + R(0.5)), fy = floor(uy / R(0.02) + R(0.5));
-    if (!(fabs(fx) <= R(25) && fabs(fy) <= R(25))) return kErrInvalidVelocity;
-    bx = fx * R(0.02);
-    by = fy * R(0.02);
-  }
-  R g[9];
-  unit_equilibrium(bx, by, g);
-  R gmin = g[0];
-#pragma unroll
-  for (int i = 1; i < 9; ++i) gmin = fmin(gmin, g[i]);
-  if (!(gmin > R(0))) return kErrInvalidVelocity;
-
-  Basis<R> B;
-  fnorm_basis(bx, by, B);
-  R Mt[6], D[6], y[6];
-  lower_solve(B, d, Mt);  // non-equilibrium f-norm moments M~^{3..8}
-#pragma unroll
-  for (int a = 0; a < 6; ++a) D[a] = C.xc[a] * N[a] - C.rt[a] * Mt[a];
-  upper_solve(B, D, y);
-  // df_i = g_i [ sum_a m_i^a y_a - A - m~^1_i B1 - m~^2_i B2 ]
-  const R A = B.P0[0] * y[0] + B.P0[1] * y[1] + B.P0[2] * y[2];
-  const R B1 = B.P1[0] * y[0] + B.P1[1] * y[1] + B.P1[2] * y[2] + B.P1[3] * y[3] +
-               B.P1[4] * y[4];
-  const R B2 = B.P2[0] * y[0] + B.P2[1] * y[1] + B.P2[2] * y[2] + B.P2[3] * y[3] +
-               B.P2[4] * y[4];
-  constexpr R S3 = R(1.7320508075688772935);
-  const R Bx = S3 * B1, By = S3 * B2;
-  const R K = (Bx * bx + By * by) - A;
+  // The Hermite rows are orthonormal under the weights w, so the change is
+  // df_i = w_i sum_a m_i^a Y_a.
   R s[9];
-  hermite_back(y, s);
-  R tt[9];
-  tt[0] = s[0] + K;
-  tt[1] = s[1] + (K - Bx);
-  tt[3] = s[3] + (K + Bx);
-  tt[2] = s[2] + (K - By);
-  tt[4] = s[4] + (K + By);
-  tt[5] = s[5] + (K - (Bx + By));
-  tt[7] = s[7] + (K + (Bx + By));
-  tt[6] = s[6] + (K + (Bx - By));
-  tt[8] = s[8] + (K - (Bx - By));
+  hermite_back(Y, s);
+  constexpr R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+  h[0] += w0 * s[0];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) h[i] += g[i] * tt[i];
+  for (int i = 1; i < 5; ++i) h[i] += w1 * s[i];
+#pragma unroll
+  for (int i = 5; i < 9; ++i) h[i] += w5 * s[i];
   return 0;
 }
 
