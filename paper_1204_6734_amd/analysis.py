@@ -179,30 +179,59 @@ def mixed_tau_statistics(F, precision: int, ux0: float, nx: int = 256, ny: int =
     ``segments`` equal time segments ("sk_segments", shape (segments, 5, ny,
     nx): rho, j~_x, j~_y, Re and Im of the cross term, each <|dA(k)|^2> /
     (nx ny)), plus the wall time of the sampled steps."""
+    return mixed_tau_statistics_many(F, precision, (ux0,), nx, ny, kT, tau, seed, therm, steps,
+                                     sk_every, segments, block_steps, basis)[0]
+
+
+def mixed_tau_statistics_many(F, precision: int, ux0s, nx: int = 256, ny: int = 256,
+                              kT: float = 1e-4, tau=None, seed: int = 1, therm: int = 20_000,
+                              steps: int = 100_000, sk_every: int = 10, segments: int = 20,
+                              block_steps: int = 5_000, basis: int = 0) -> list:
+    """`mixed_tau_statistics` for several background flows at once: one
+    lattice per u_x0, each on its own stream, stepped side by side.  A small
+    lattice is one wavefront per SIMD, so its step is held by latency;
+    lattices on separate streams overlap on the device, and each replays
+    captured graphs of whole multiples of ``sk_every`` steps (the sampled
+    and structure-factor steps inside them), so the host keeps up.  Every
+    lattice computes exactly what it computes alone; "seconds" is the wall
+    time of the sampled steps of all of them together."""
     if tau is None:
         from . import inputs
         tau = inputs.mixed_taus(2)
     if therm % sk_every or steps % (segments * sk_every):
         raise ValueError("therm and steps / segments must be multiples of sk_every")
-    p = F.make_params(nx, ny, precision=precision, basis=basis, rho0=1.0, ux0=ux0, kT=kT,
-                      tau=tau, seed=seed, sample_every=1, block_steps=block_steps,
-                      sk_every=sk_every)
-    L = F.Lattice(p)
-    L.step(therm)
-    L.reset_stats()
+    chunk = 2 * sk_every * max(1, 50 // sk_every)  # even, a multiple of sk_every
+    lats = []
+    for u in ux0s:
+        p = F.make_params(nx, ny, precision=precision, basis=basis, rho0=1.0, ux0=float(u), kT=kT,
+                          tau=tau, seed=seed, sample_every=1, block_steps=block_steps,
+                          sk_every=sk_every)
+        L = F.Lattice(p)
+        L.set_graph_chunk(chunk)
+        lats.append(L)
+    for L in lats:
+        L.step(therm)
+    for L in lats:
+        L.reset_stats()
     seg = steps // segments
     per = seg // sk_every  # structure-factor samples per segment
-    sums_prev = np.zeros((5, ny, nx))
-    out = np.empty((segments, 5, ny, nx))
+    sums_prev = [np.zeros((5, ny, nx)) for _ in lats]
+    out = [np.empty((segments, 5, ny, nx)) for _ in lats]
     t0 = time.perf_counter()
     for s in range(segments):
-        L.step(seg)
-        sums = np.stack([L.structure_factor(w) for w in range(5)]) * ((s + 1) * per)
-        out[s] = (sums - sums_prev) / per
-        sums_prev = sums
-    L.sync()
+        for L in lats:
+            L.step(seg)
+        for i, L in enumerate(lats):
+            sums = np.stack([L.structure_factor(w) for w in range(5)]) * ((s + 1) * per)
+            out[i][s] = (sums - sums_prev[i]) / per
+            sums_prev[i] = sums
+    for L in lats:
+        L.sync()
     dt = time.perf_counter() - t0
-    cov = L.covariance()
-    L.close()
-    return {"cov": cov, "sk_segments": out, "seconds": dt, "nx": nx, "ny": ny, "steps": steps,
-            "therm": therm, "ux0": ux0, "kT": kT, "tau": list(tau), "seed": seed}
+    res = []
+    for i, (L, u) in enumerate(zip(lats, ux0s)):
+        res.append({"cov": L.covariance(), "sk_segments": out[i], "seconds": dt, "nx": nx,
+                    "ny": ny, "steps": steps, "therm": therm, "ux0": float(u), "kT": kT,
+                    "tau": list(tau), "seed": seed, "lattices_together": len(lats)})
+        L.close()
+    return res

@@ -62,11 +62,30 @@ _runs = {}
 
 
 def run(flb, prec, u, kT=1e-4, seed=1):
-    key = (prec, u, kT, seed)
+    # the three background flows of one precision run side by side
+    key = (prec, kT, seed)
     if key not in _runs:
         precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
-        _runs[key] = A.mixed_tau_statistics(flb, precision, float(u), kT=kT, seed=seed)
-    return _runs[key]
+        rs = A.mixed_tau_statistics_many(flb, precision, [float(v) for v in U0], kT=kT, seed=seed)
+        _runs[key] = dict(zip(U0, rs))
+    return _runs[key][u]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lattices_side_by_side_compute_what_they_compute_alone(flb, prec):
+    """Three lattices stepped side by side on their own streams, each
+    replaying captured graphs, give bit for bit the correlators, time blocks
+    and structure-factor segments of the same lattices run one at a time."""
+    precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+    kw = dict(nx=64, ny=48, therm=200, steps=1000, sk_every=10, segments=5, block_steps=200)
+    many = A.mixed_tau_statistics_many(flb, precision, (0.0, 0.1, 0.2), **kw)
+    for r in many:
+        alone = A.mixed_tau_statistics(flb, precision, r["ux0"], **kw)
+        assert r["lattices_together"] == 3 and alone["lattices_together"] == 1
+        for k, v in alone["cov"].items():
+            np.testing.assert_array_equal(r["cov"][k], v, err_msg=f"u0 {r['ux0']} {k}")
+        np.testing.assert_array_equal(r["sk_segments"], alone["sk_segments"])
+        assert r["cov"]["nsamples"] == 1000 * 64 * 48 and r["cov"]["nblocks"] == 5
 
 
 @pytest.mark.parametrize("u", U0)
