@@ -45,12 +45,13 @@ BYTES_PER_SITE = {"f32": 72, "f64": 144}
 # site), SQ_INSTS_VALU / SQ_WAVES averaged over both phases,
 # profiles/step3_fp32_256cube_d3q19.md
 D3Q19_VALU_PER_SITE = 2297
-# FP32 floating-point operations per site of that kernel, counted in its
-# gfx950 code: FMAs 2 each (1624 v_fma/v_fmac/v_fmamk), multiplies, adds and
-# subtracts 1 each (254 + 85), transcendentals (rsq, rcp, sqrt, log, sin,
+# FP32 floating-point operations per site of that kernel (its variant for
+# one relaxation time, which this workload's tau = 1 selects), counted in its
+# gfx950 code: FMAs 2 each (1519 v_fma/v_fmac/v_fmamk), multiplies, adds and
+# subtracts 1 each (225 + 85), transcendentals (rsq, rcp, sqrt, log, sin,
 # cos) 1 each (48); conversions, compares and min/max are not counted.  One
 # lane computes one site.
-D3Q19_FLOPS_PER_SITE = 3635
+D3Q19_FLOPS_PER_SITE = 3396
 # FP32 vector peak without packed (two-wide) instructions, which this
 # library does not use: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9

@@ -111,12 +111,16 @@ struct Lattice3 {
     h.u0[2] = p.uz0;
     h.rho0f = (float)p.rho0;
     for (int a = 0; a < 3; ++a) h.u0f[a] = (float)h.u0[a];
+    h.one_tau = 1;
     for (int a = 0; a < 15; ++a) {
       h.rt[a] = 1.0 / p.tau[a];
       h.xc[a] = std::sqrt(mu * (2 * p.tau[a] - 1)) / p.tau[a];
       h.rtf[a] = (float)h.rt[a];
       h.xcf[a] = (float)h.xc[a];
+      if (p.tau[a] != p.tau[0]) h.one_tau = 0;
     }
+    h.xc2 = mu * (2 * p.tau[0] - 1) / (p.tau[0] * p.tau[0]);
+    h.xc2f = (float)h.xc2;
     for (int i = 0; i < 19; ++i) h.shift[i] = equilibrium3(i, p.rho0, h.u0);
     // one allocation: descriptor, clock, error flags, populations, partials,
     // time-block records, open sums
@@ -207,8 +211,8 @@ struct Lattice3 {
           HIPC(hipEventCreate(&ev.second));
           HIPC(hipEventRecord(ev.first, st));
         }
-        HIPC(launch_step3(storage, p.basis == FLB_BASIS_HERMITE ? 1 : 0, sample, (int)(tt & 1),
-                          h.ntiles, d_desc, d_clock, (uint32_t)k, st));
+        HIPC(launch_step3(storage, p.basis == FLB_BASIS_HERMITE ? 1 : 0, h.one_tau != 0, sample,
+                          (int)(tt & 1), h.ntiles, d_desc, d_clock, (uint32_t)k, st));
         if (profiling) {
           HIPC(hipEventRecord(ev.second, st));
           events.push_back(ev);

@@ -29,6 +29,8 @@ template <typename R>
 struct Const3 {
   R rho0, u0[3];
   R rt[15], xc[15];  // 1/tau, xi / sqrt(rho)
+  R xc2;             // xc^2 when one_tau
+  int one_tau;       // the fifteen relaxation times are equal
 };
 
 template <typename R>
@@ -42,6 +44,8 @@ __device__ __forceinline__ Const3<float> const3<float>(const Desc3& d) {
     c.rt[a] = d.rtf[a];
     c.xc[a] = d.xcf[a];
   }
+  c.xc2 = d.xc2f;
+  c.one_tau = d.one_tau;
   return c;
 }
 template <>
@@ -53,6 +57,8 @@ __device__ __forceinline__ Const3<double> const3<double>(const Desc3& d) {
     c.rt[a] = d.rt[a];
     c.xc[a] = d.xc[a];
   }
+  c.xc2 = d.xc2;
+  c.one_tau = d.one_tau;
   return c;
 }
 
@@ -240,6 +246,62 @@ __device__ __forceinline__ int collide3_hermite(R h[19], const Const3<R>& C, int
 }
 
 constexpr int kBlock3 = 256;   // threads per workgroup (one 64 x 4 tile)
+// The factor L of the Schur complement G' = <m^a, m^b>_g - P0 P0^T -
+// sum_a P_a P_a^T, one column at a time (packed lower part L[i(i+1)/2 + k]),
+// and Y = L dM~ accumulated alongside: column j gives the pivot q and its
+// inverse square root r, the column of L, and the contribution L_ij dM~_j
+// to Y_i for i >= j (L_jj = q r); each row of the factor is dropped when its
+// column is done.  dM~_j = -M~_j / tau_j + xi_j N_j needs the forward solve
+// M~ = L^-1 d in column form (M~_j = d_j r, then d_i -= L_ij M~_j for i > j).
+// With one relaxation time (ONE, N carrying xi) there is no solve:
+// L (M~ / tau) = d / tau, so Y = L (xi N) - d / tau.
+template <typename R, bool ONE>
+__device__ __forceinline__ void factor_relax(const R mono[9], R uu, const R P0[15],
+                                             const R P[3][15], R d[15], const R N[15],
+                                             const Const3<R>& C, R Y[15]) {
+  R L[120];
+#pragma unroll
+  for (int j = 0; j < 15; ++j) {
+#pragma unroll
+    for (int i = j; i < 15; ++i) {
+      R G = i == j ? R(1) - R(1.5) * uu : R(0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if (kG3[4 + i][4 + j][k] != 0.0) G += R(kG3[4 + i][4 + j][k]) * mono[k];
+      G = fma(-P0[i], P0[j], G);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) G = fma(-P[c][i], P[c][j], G);
+#pragma unroll
+      for (int k = 0; k < j; ++k) G -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+      L[i * (i + 1) / 2 + j] = G;
+    }
+    const R q = L[j * (j + 1) / 2 + j];
+    const R r = rsqrt_t(q);
+    R D;
+    if constexpr (ONE) {
+#pragma unroll
+      for (int i = j + 1; i < 15; ++i) L[i * (i + 1) / 2 + j] *= r;
+      D = N[j];
+    } else {
+      const R mj = d[j] * r;
+#pragma unroll
+      for (int i = j + 1; i < 15; ++i) {
+        L[i * (i + 1) / 2 + j] *= r;
+        d[i] -= L[i * (i + 1) / 2 + j] * mj;
+      }
+      D = C.xc[j] * N[j] - C.rt[j] * mj;
+    }
+    Y[j] = j == 0 ? (q * r) * D : Y[j] + (q * r) * D;
+#pragma unroll
+    for (int i = j + 1; i < 15; ++i)
+      Y[i] = j == 0 ? L[i * (i + 1) / 2 + j] * D : Y[i] + L[i * (i + 1) / 2 + j] * D;
+  }
+  if constexpr (ONE) {
+#pragma unroll
+    for (int i = 0; i < 15; ++i) Y[i] = Y[i] - C.rt[0] * d[i];
+  }
+}
+
 // The f-norm collision (BASIS 0).  The change of the populations is
 // df = sum_{a >= 4} n~^a dM~^a with n~^a = m~^a g and dM~^a = -M~^a / tau^a +
 // xi^a N^a (eqs. (6), (20)): a g-weighted combination of the rows 4..18
@@ -249,12 +311,10 @@ constexpr int kBlock3 = 256;   // threads per workgroup (one 64 x 4 tile)
 // the projected rows).  The rows are orthonormal under the weights w, so
 // df_i = w_i sum_b m^b_i (L dM~)_b, the back-transform of the Hermite-type
 // collision.  L dM~ is accumulated column by column inside the Cholesky
-// sweep, which also forms the Schur complement one column at a time and
-// takes the forward solve M~ = L^-1 d in column form, so each row of the
-// factor is dropped as soon as its column is done.  Returns error bits; hout
+// sweep (factor_relax).  Returns error bits; hout
 // is written only on success (on failure the caller reads the site's values
 // again).
-template <typename R>
+template <typename R, bool ONE>
 __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C, int noise,
                                               const R Nu[15], R hout[19]) {
   R M[19];
@@ -282,8 +342,10 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
     return kErrNonFinite;
   if (!(gmin > R(0))) return kErrInvalidVelocity;
 
+  // with one relaxation time the Gaussians carry the common coefficient too:
+  // xi N = sqrt(xc^2 rho) N
   R N[15];
-  scaled_noise(noise, rho, Nu, N);
+  scaled_noise(noise, ONE ? C.xc2 * rho : rho, Nu, N);
 
   const R mono[9] = {u[0], u[1], u[2], u[0] * u[0], u[1] * u[1], u[2] * u[2],
                      u[0] * u[1], u[0] * u[2], u[1] * u[2]};
@@ -313,41 +375,8 @@ __device__ __forceinline__ int collide3_fnorm(const R h[19], const Const3<R>& C,
       P[a][b - 4] = ga - R(kS3) * u[a] * pi;
     }
   }
-  // Column j: the column of G' = <m^a, m^b>_g - P0 P0^T - sum_a P_a P_a^T
-  // less the columns of L before it (packed lower part L[i(i+1)/2 + k]), the
-  // pivot q and its inverse square root r, the column of L, the forward-solve
-  // step (M~_j = d_j r, then d_i -= L_ij M~_j for i > j), the relaxation
-  // dM~_j, and its contribution L_ij dM~_j to Y_i for i >= j (L_jj = q r).
-  R L[120], Y[15];
-#pragma unroll
-  for (int j = 0; j < 15; ++j) {
-#pragma unroll
-    for (int i = j; i < 15; ++i) {
-      R G = i == j ? R(1) - R(1.5) * uu : R(0);
-#pragma unroll
-      for (int k = 0; k < 9; ++k)
-        if (kG3[4 + i][4 + j][k] != 0.0) G += R(kG3[4 + i][4 + j][k]) * mono[k];
-      G = fma(-P0[i], P0[j], G);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) G = fma(-P[c][i], P[c][j], G);
-#pragma unroll
-      for (int k = 0; k < j; ++k) G -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
-      L[i * (i + 1) / 2 + j] = G;
-    }
-    const R q = L[j * (j + 1) / 2 + j];
-    const R r = rsqrt_t(q);
-    const R mj = d[j] * r;
-#pragma unroll
-    for (int i = j + 1; i < 15; ++i) {
-      L[i * (i + 1) / 2 + j] *= r;
-      d[i] -= L[i * (i + 1) / 2 + j] * mj;
-    }
-    const R D = C.xc[j] * N[j] - C.rt[j] * mj;
-    Y[j] = j == 0 ? (q * r) * D : Y[j] + (q * r) * D;
-#pragma unroll
-    for (int i = j + 1; i < 15; ++i)
-      Y[i] = j == 0 ? L[i * (i + 1) / 2 + j] * D : Y[i] + L[i * (i + 1) / 2 + j] * D;
-  }
+  R Y[15];
+  factor_relax<R, ONE>(mono, uu, P0, P, d, N, C, Y);
   R sg[19];
   back3(Y, sg);
 #pragma unroll
@@ -441,7 +470,7 @@ constexpr int waves3() {
 // per-lane part of an offset is one of three columns x - 1, x, x + 1; the
 // row part (nine distinct (y, z) shifts) is scalar.  Tiles are renumbered
 // so that each XCD sweeps a contiguous range of z planes.
-template <typename S, typename R, int BASIS, bool SAMPLE, int ODD>
+template <typename S, typename R, int BASIS, bool SAMPLE, int ODD, bool ONE>
 __global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(waves3<R>()))) void
 step3_kernel(const Desc3* __restrict__ desc, const uint64_t* __restrict__ clock,
              uint32_t step_idx) {
@@ -497,7 +526,7 @@ step3_kernel(const Desc3* __restrict__ desc, const uint64_t* __restrict__ clock,
   R hn[19];
   int e;
   if constexpr (BASIS == 0) {
-    e = collide3_fnorm<R>(h, C, d.noise, Nu, hn);
+    e = collide3_fnorm<R, ONE>(h, C, d.noise, Nu, hn);
   } else {
     e = collide3_hermite<R, !kEarlyNoise>(h, C, d.noise, Nu, d.k0, d.k1, cell(x, y, z, d), t);
 #pragma unroll
@@ -575,31 +604,36 @@ __global__ void fill3_kernel(double* p, size_t n) {
 }
 
 // ------------------------------------------------------------- launchers
-template <typename S, typename R, int BASIS>
+template <typename S, typename R, int BASIS, bool ONE>
 static hipError_t step3_t(bool sample, int odd, int ntiles, const Desc3* d,
                           const uint64_t* clock, uint32_t k, hipStream_t st) {
   const dim3 g(ntiles), b(kBlock3);
   if (sample) {
     if (odd)
-      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, true, 1>), g, b, 0, st, d, clock, k);
+      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, true, 1, ONE>), g, b, 0, st, d, clock, k);
     else
-      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, true, 0>), g, b, 0, st, d, clock, k);
+      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, true, 0, ONE>), g, b, 0, st, d, clock, k);
   } else {
     if (odd)
-      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, false, 1>), g, b, 0, st, d, clock, k);
+      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, false, 1, ONE>), g, b, 0, st, d, clock, k);
     else
-      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, false, 0>), g, b, 0, st, d, clock, k);
+      hipLaunchKernelGGL((step3_kernel<S, R, BASIS, false, 0, ONE>), g, b, 0, st, d, clock, k);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step3(int storage, int basis, bool sample, int odd, int ntiles, const Desc3* d,
-                        const uint64_t* clock, uint32_t k, hipStream_t st) {
-  if (storage == 0)
-    return basis == 1 ? step3_t<double, double, 1>(sample, odd, ntiles, d, clock, k, st)
-                      : step3_t<double, double, 0>(sample, odd, ntiles, d, clock, k, st);
-  return basis == 1 ? step3_t<float, float, 1>(sample, odd, ntiles, d, clock, k, st)
-                    : step3_t<float, float, 0>(sample, odd, ntiles, d, clock, k, st);
+template <typename S>
+static hipError_t step3_s(int basis, bool one_tau, bool sample, int odd, int ntiles,
+                          const Desc3* d, const uint64_t* clock, uint32_t k, hipStream_t st) {
+  if (basis == 1) return step3_t<S, S, 1, false>(sample, odd, ntiles, d, clock, k, st);
+  if (one_tau) return step3_t<S, S, 0, true>(sample, odd, ntiles, d, clock, k, st);
+  return step3_t<S, S, 0, false>(sample, odd, ntiles, d, clock, k, st);
+}
+
+hipError_t launch_step3(int storage, int basis, bool one_tau, bool sample, int odd, int ntiles,
+                        const Desc3* d, const uint64_t* clock, uint32_t k, hipStream_t st) {
+  if (storage == 0) return step3_s<double>(basis, one_tau, sample, odd, ntiles, d, clock, k, st);
+  return step3_s<float>(basis, one_tau, sample, odd, ntiles, d, clock, k, st);
 }
 
 hipError_t launch_io3(int storage, void* pop, double* f, const Desc3& d, int odd, int to_storage,

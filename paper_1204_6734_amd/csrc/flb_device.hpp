@@ -271,8 +271,10 @@ struct CollideConst {
   R rho0, ux0, uy0;
   R rt[6];     // 1/tau^a, a = 3..8
   R xc[6];     // sqrt(mu (2 tau^a - 1)) / tau^a: xi^a = sqrt(rho) xc^a (eq. (20))
+  R xc2;       // xc^2 when one_tau
   uint32_t k0, k1;
   int noise;   // 0 when kT == 0
+  int one_tau; // the six relaxation times are equal
 };
 
 // Hermite moments (rows of eq. (A3)) of the shifted populations h; the
@@ -588,9 +590,12 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C,
   const R ux = S.ux, uy = S.uy;
   const R* d = S.d;
 
+  // With one relaxation time the f-norm collision scales the Gaussians by
+  // the common coefficient as well: xi N = sqrt(xc^2 rho) N.
+  const bool one = BASIS != kBasisHermite && C.one_tau;
   R N[6];
   if (C.noise) {
-    scaled_noise(draw, S.rho, N);
+    scaled_noise(draw, one ? C.xc2 * S.rho : S.rho, N);
   } else {
 #pragma unroll
     for (int a = 0; a < 6; ++a) N[a] = R(0);
@@ -620,11 +625,20 @@ __device__ __forceinline__ int collide(R h[9], const CollideConst<R>& C,
     // coefficients of the projected rows).
     Basis<R> B;
     fnorm_basis(bx, by, B);
-    R Mt[6], D[6];
-    lower_solve(B, d, Mt);  // non-equilibrium f-norm moments M~^{3..8}
+    if (one) {
+      // One relaxation time: L (M~ / tau) = d / tau, so only the noise needs
+      // the factor, Y = L (xi N) - d / tau.
+      R LN[6];
+      lower_mul(B, N, LN);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) D[a] = C.xc[a] * N[a] - C.rt[a] * Mt[a];
-    lower_mul(B, D, Y);
+      for (int a = 0; a < 6; ++a) Y[a] = LN[a] - C.rt[0] * d[a];
+    } else {
+      R Mt[6], D[6];
+      lower_solve(B, d, Mt);  // non-equilibrium f-norm moments M~^{3..8}
+#pragma unroll
+      for (int a = 0; a < 6; ++a) D[a] = C.xc[a] * N[a] - C.rt[a] * Mt[a];
+      lower_mul(B, D, Y);
+    }
   }
   // The Hermite rows are orthonormal under the weights w, so the change is
   // df_i = w_i sum_a m_i^a Y_a.

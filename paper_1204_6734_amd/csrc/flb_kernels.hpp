@@ -45,11 +45,12 @@ struct SlotDesc {
   int noise;
   uint32_t pitch;       // elements per plane row (nx rounded up to kTileX)
   int wide;             // tile shape: 1 = 256 x 1 (four wavefronts along one row), 0 = 64 x 4
-  int pad_;
+  int one_tau;          // all six relaxation times equal
   double rho0, ux0, uy0;
   double rt[6], xc[6];  // 1/tau, noise coefficients
+  double xc2;           // mu (2 tau - 1) / tau^2 = xc^2 when one_tau
   double shift[9];      // f_i^0(rho0, u0): storage holds h = f - shift
-  float rho0f, ux0f, uy0f, padf_;  // single-precision copies
+  float rho0f, ux0f, uy0f, xc2f;  // single-precision copies
   float rtf[6], xcf[6], shiftf[9];
 };
 

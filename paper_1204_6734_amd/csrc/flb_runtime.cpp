@@ -199,13 +199,17 @@ void fill_slot(const flb_params* p, SlotDesc* d) {
   d->rho0f = (float)p->rho0;
   d->ux0f = (float)p->ux0;
   d->uy0f = (float)p->uy0;
+  d->one_tau = 1;
   for (int a = 0; a < 6; ++a) {
     const double tau = p->tau[a];
     d->rt[a] = 1.0 / tau;
     d->xc[a] = std::sqrt(mu * (2 * tau - 1)) / tau;
     d->rtf[a] = (float)d->rt[a];
     d->xcf[a] = (float)d->xc[a];
+    if (tau != p->tau[0]) d->one_tau = 0;
   }
+  d->xc2 = mu * (2 * p->tau[0] - 1) / (p->tau[0] * p->tau[0]);
+  d->xc2f = (float)d->xc2;
   for (int i = 0; i < 9; ++i) {
     d->shift[i] = equilibrium(i, p->rho0, p->ux0, p->uy0);
     d->shiftf[i] = (float)d->shift[i];

@@ -57,6 +57,8 @@ __device__ __forceinline__ CollideConst<float> collide_const<float>(const SlotDe
     C.rt[a] = sd.rtf[a];
     C.xc[a] = sd.xcf[a];
   }
+  C.xc2 = sd.xc2f;
+  C.one_tau = sd.one_tau;
   C.k0 = sd.k0;
   C.k1 = sd.k1;
   C.noise = sd.noise;
@@ -74,6 +76,8 @@ __device__ __forceinline__ CollideConst<double> collide_const<double>(const Slot
     C.rt[a] = sd.rt[a];
     C.xc[a] = sd.xc[a];
   }
+  C.xc2 = sd.xc2;
+  C.one_tau = sd.one_tau;
   C.k0 = sd.k0;
   C.k1 = sd.k1;
   C.noise = sd.noise;

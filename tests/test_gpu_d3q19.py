@@ -107,6 +107,37 @@ def test_fp32_shifted_matches_fp64_oracle(flb, basis):
     assert err <= 1e-5, (basis, err)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_one_relaxation_time_matches_oracle(flb, prec):
+    """All fifteen relaxation times equal (0.8): the f-norm collision takes
+    L (M~ / tau) = d / tau without the forward solve and scales the
+    Gaussians by the common coefficient.  FP64 against the oracle to 1e-12
+    from perturbed equilibria at both streaming phases; FP32-shifted storage
+    on the fluctuations to 1e-5 after 200 steps."""
+    nx, ny, nz = 70, 6, 5
+    kw = dict(ux0=0.1, uy0=-0.05, uz0=0.03, kT=1e-4, tau=(0.8,) * 15, seed=9)
+    if prec == "fp64":
+        g, o = both(flb, nx, ny, nz, flb.FP64, flb.BASIS_FNORM_LOCAL, **kw)
+        f = perturbed(nx, ny, nz, (0.1, -0.05, 0.03))
+        g.set_populations(f)
+        o.set_populations(f)
+        for n in (1, 1, 23):
+            g.step(n)
+            o.step(n)
+            fg, fo = g.populations(), o.populations()
+            err = np.abs(fg - fo).max() / np.abs(fo).max()
+            assert err <= 1e-12, (o.t, err)
+    else:
+        g, o = both(flb, nx, ny, nz, flb.FP32_SHIFTED, flb.BASIS_FNORM_LOCAL, **kw)
+        g.step(200)
+        o.step(200)
+        f0 = D.equilibrium(1.0, 0.1, -0.05, 0.03)[:, None, None, None]
+        dg, do = g.populations() - f0, o.populations() - f0
+        err = np.abs(dg - do).max() / np.abs(do).max()
+        print(f"one tau: max |df_gpu - df_oracle| / max |df| = {err:.2e}")
+        assert err <= 1e-5, err
+
+
 @pytest.mark.parametrize("basis", ["fnorm", "hermite"])
 def test_fp32_correlator_sums_match_oracle(flb, basis):
     """The correlator sums of an FP32-shifted lattice (values staged in FP32,

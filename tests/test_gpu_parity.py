@@ -103,6 +103,58 @@ def test_table_basis_tie_takes_either_neighbour(flb):
     assert min(np.abs(mine - O.collide_lut_at(p, f0, ix, iy)).max() for ix, iy in cands) == 0.0
 
 
+# One relaxation time for all six non-conserved modes.  The f-norm collision
+# then takes L (M~ / tau) = d / tau without the forward solve and scales the
+# Gaussians by the common noise coefficient before their product with L.
+ONE_TAU = (0.8,) * 6
+
+
+@pytest.mark.parametrize("basis", ["fnorm", "lut"])
+@pytest.mark.parametrize("sample_every", [0, 1])
+def test_one_relaxation_time_fp64_matches_oracle(flb, basis, sample_every):
+    """FP64 trajectories from random fields with tau^a = 0.8 for all six
+    modes, in the plain and in the sampling step, to 1e-12 at both streaming
+    phases and after 1000 steps; then, from equilibrium, the first step's
+    change (the noise term alone) to 1e-12."""
+    b = BASES[basis][0]
+    nx, ny = 70, 9
+    kw = dict(rho0=1.0, ux0=0.1, uy0=-0.05, kT=1e-4, tau=ONE_TAU, seed=7, init=2,
+              sample_every=sample_every, block_steps=100)
+    g, o = both(flb, nx, ny, flb.FP64, b, **kw)
+    fields = I.random_fields(nx, ny, seed=5, ux0=0.1, uy0=-0.05)
+    g.set_fields(*fields)
+    o.set_fields(*fields)
+    for n in (1, 1, 3, 95, 900):
+        g.step(n)
+        o.step(n)
+        err = rel(g.populations(), o.populations())
+        assert err <= 1e-12, (basis, o.t, err)
+    kw = dict(rho0=1.0, ux0=0.08, uy0=-0.025, kT=1e-3, tau=ONE_TAU, seed=21)
+    g, o = both(flb, nx, ny, flb.FP64, b, **kw)
+    f0 = O.equilibrium(1.0, 0.08, -0.025)[:, None, None]
+    for k in range(2):
+        g.step(1)
+        o.step(1)
+        err = rel(g.populations() - f0, o.populations() - f0)
+        assert err <= 1e-12, (basis, k, err)
+
+
+@pytest.mark.parametrize("basis", ["fnorm", "lut"])
+@pytest.mark.parametrize("ux0,uy0", [(0.1, 0.0), (0.3, 0.1)])
+def test_one_relaxation_time_fp32_matches_oracle(flb, basis, ux0, uy0):
+    """FP32-shifted storage with tau^a = 0.8 for all six modes, with the FP32
+    collision (u0 = 0.1) and the FP64 one (u0 = 0.3): every moment at u0 to
+    1e-5 of its largest value after 1000 steps against the oracle."""
+    kw = dict(ux0=ux0, uy0=uy0, kT=FP32_KT[basis], tau=ONE_TAU, seed=11)
+    g, o = both(flb, 100, 30, flb.FP32_SHIFTED, BASES[basis][0], **kw)
+    g.step(1000)
+    o.step(1000)
+    mg, mo = g.moments(flb.AT_U0), o.moments(flb.AT_U0)
+    worst = max(np.abs(mg[a] - mo[a]).max() / np.abs(mo[a]).max() for a in range(9))
+    print(f"{basis} u0 ({ux0}, {uy0}), one tau: worst moment rel err {worst:.2e}")
+    assert worst <= 1e-5, worst
+
+
 @pytest.mark.parametrize("nx,ny", [(3, 3), (3, 17), (65, 3), (64, 4), (4, 65)])
 def test_degenerate_shapes_match_oracle(flb, nx, ny):
     """The smallest lattices and thin ones: a single partly filled tile whose
