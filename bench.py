@@ -44,7 +44,7 @@ BYTES_PER_SITE = {"f32": 72, "f64": 144}
 # D3Q19 FP32 f-norm step: VALU wavefront instructions per wavefront (= per
 # site), SQ_INSTS_VALU / SQ_WAVES averaged over both phases,
 # profiles/step3_fp32_256cube_d3q19.md
-D3Q19_VALU_PER_SITE = 2297
+D3Q19_VALU_PER_SITE = 2095
 # FP32 floating-point operations per site of that kernel (its variant for
 # one relaxation time, which this workload's tau = 1 selects), counted in its
 # gfx950 code: FMAs 2 each (1519 v_fma/v_fmac/v_fmamk), multiplies, adds and

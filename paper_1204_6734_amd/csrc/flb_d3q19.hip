@@ -260,6 +260,11 @@ __device__ __forceinline__ void factor_relax(const R mono[9], R uu, const R P0[1
                                              const R P[3][15], R d[15], const R N[15],
                                              const Const3<R>& C, R Y[15]) {
   R L[120];
+  if constexpr (ONE) {
+    // -d / tau first, so that d is not held through the sweep
+#pragma unroll
+    for (int i = 0; i < 15; ++i) Y[i] = -(C.rt[0] * d[i]);
+  }
 #pragma unroll
   for (int j = 0; j < 15; ++j) {
 #pragma unroll
@@ -291,14 +296,10 @@ __device__ __forceinline__ void factor_relax(const R mono[9], R uu, const R P0[1
       }
       D = C.xc[j] * N[j] - C.rt[j] * mj;
     }
-    Y[j] = j == 0 ? (q * r) * D : Y[j] + (q * r) * D;
+    Y[j] = j == 0 && !ONE ? (q * r) * D : Y[j] + (q * r) * D;
 #pragma unroll
     for (int i = j + 1; i < 15; ++i)
-      Y[i] = j == 0 ? L[i * (i + 1) / 2 + j] * D : Y[i] + L[i * (i + 1) / 2 + j] * D;
-  }
-  if constexpr (ONE) {
-#pragma unroll
-    for (int i = 0; i < 15; ++i) Y[i] = Y[i] - C.rt[0] * d[i];
+      Y[i] = j == 0 && !ONE ? L[i * (i + 1) / 2 + j] * D : Y[i] + L[i * (i + 1) / 2 + j] * D;
   }
 }
 
