@@ -14,8 +14,10 @@
 // are quadratic polynomials in u (G) and the projections P of the Hermite
 // rows on the conserved rows (cubic).  Classical Gram-Schmidt with positive
 // normalisation is exactly m~^{3..8} = L^-1 (m^{3..8} - projections), so
-//   M~^{3..8} = L^-1 d,  d = Hermite non-equilibrium moments M - M^0(rho,u),
-//   df = D_g p^T L^-T dM~.
+//   M~^{3..8} = L^-1 d,  d = Hermite non-equilibrium moments M - M^0(rho,u).
+// The change df = sum_a m~^a g dM~^a has Hermite moments L dM~ (and no
+// conserved ones), so df_i = w_i sum_a m_i^a (L dM~)_a; with one relaxation
+// time for all six modes, L dM~ = L (xi N) - d / tau needs no solve at all.
 // Nothing is tabulated and no 9x9 product is formed.
 #pragma once
 

@@ -35,6 +35,23 @@ def test_traffic_is_used_only_for_the_profiled_sources(tmp_path, monkeypatch):
     assert bench.traffic_from_profiles("step_fp64_8192") is None
 
 
+def test_kernel_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    """The sources hash that keys the counter record changes with the code of
+    the step kernel's sources and not with their comments or layout."""
+    src = tmp_path / "k.hip"
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", ["k.hip"])
+
+    def h(text):
+        src.write_text(text)
+        return bench.kernel_hash()
+
+    base = h("// step\nint f(int x) {\n  return x + 1;  // one\n}\n")
+    assert h("/* the step,\n   reworded */\nint f(int x) {\n    return x + 1;\n}\n") == base
+    assert h("// step\nint f(int x) {\n  return x + 2;  // one\n}\n") != base
+    assert h("// step\nint f(int x) {\n  return x - 1;  // one\n}\n") != base
+
+
 def test_cpu_baseline_record():
     """The oracle on every host core (the threads it used are `cores`), with
     the single-thread rate beside it."""
