@@ -72,7 +72,10 @@ typedef struct {
   double ux0, uy0;      /* background velocity (inside the validity region)       */
   double kT;            /* noise temperature (>= 0); mu = 3 kT                    */
   double tau[6];        /* relaxation times of modes 3..8 (Pi_xx-yy, Pi_xy,
-                           Pi_xx+yy, q_x, q_y, eps), each > 1/2                   */
+                           Pi_xx+yy, q_x, q_y, eps), each > 1/2.  When all six
+                           are equal the f-norm collision takes a shorter form
+                           (L M~ / tau = d / tau: no triangular solve), equal to
+                           the general one up to rounding                       */
   uint64_t seed;        /* Philox key: noise is keyed by (seed, step, site)       */
   int32_t precision;    /* flb_precision.  FP32_SHIFTED stores f - f^0(rho0, u0) in
                            FP32 and collides in FP32 up to |u0| = 0.25, above it in
@@ -360,7 +363,8 @@ typedef struct {
   int32_t pad_;
   double rho0, ux0, uy0, uz0;
   double kT;               /* mu = 3 kT                                            */
-  double tau[15];          /* modes a = 4..18, each > 1/2                          */
+  double tau[15];          /* modes a = 4..18, each > 1/2; all equal: the shorter
+                              f-norm form without the triangular solve          */
   uint64_t seed;
 } flb3_params;
 
