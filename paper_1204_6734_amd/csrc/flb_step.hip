@@ -196,19 +196,35 @@ __device__ __forceinline__ void wave_correlators(const R h[9], int sub, int wave
     // the result is written over the staged values: every read above is
     // issued first (the compiler may not move the writes before them)
     asm volatile("" ::: "memory");
-    // one accumulator: the eighteen products in a fixed order
-    float4_v acc = {0.f, 0.f, 0.f, 0.f};
+    // X^T X = sum over part pairs (p, q) of X_p^T X_q, and the (q, p) term is
+    // the transpose of the (p, q) one: A holds the pairs p = q, B those with
+    // p < q, and the sum is A + B + B^T.  The pair (2, 2) is left out: its
+    // products are below 2^-30 of the others', under the rounding of the
+    // FP32 accumulators.  Ten products per wavefront, in a fixed order.
+    float4_v acc = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh)
+    for (int hh = 0; hh < 2; ++hh) {
+      const bf16x8_v x0 = __builtin_bit_cast(bf16x8_v, X[0][hh]);
+      const bf16x8_v x1 = __builtin_bit_cast(bf16x8_v, X[1][hh]);
+      const bf16x8_v x2 = __builtin_bit_cast(bf16x8_v, X[2][hh]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, x0, acc, 0, 0, 0);
+      accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, x1, accb, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, x1, acc, 0, 0, 0);
+      accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, x2, accb, 0, 0, 0);
+      accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, x2, accb, 0, 0, 0);
+    }
+    // B^T through LDS: B goes past the 2 KiB of the result, in the staging
+    // area the operands were read from, and comes back transposed
+    static_assert(sample_wave_bytes<S>() >= 2048 + 16 * 16 * (int)sizeof(float),
+                  "B fits the staging area after the result");
+    float* bt = reinterpret_cast<float*>(reinterpret_cast<char*>(out) + 2048);
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
+    for (int r = 0; r < 4; ++r) bt[(4 * grp + r) * 16 + col] = accb[r];
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_v, X[p][hh]),
-                                                         __builtin_bit_cast(bf16x8_v, X[q][hh]),
-                                                         acc, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) out[(4 * grp + r) * 16 + col] = (double)acc[r];
+    for (int r = 0; r < 4; ++r)
+      out[(4 * grp + r) * 16 + col] =
+          (double)((acc[r] + accb[r]) + bt[col * 16 + 4 * grp + r]);
   } else {
     S* x = reinterpret_cast<S*>(out);
 #pragma unroll
