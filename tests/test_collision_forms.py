@@ -11,13 +11,15 @@ sum_a n~^a dM~^a with n~^a = m~^a g.  The kernels instead:
    its Hermite moments on rows 3..8 are L dM~;
 3. with one relaxation time, L dM~ = L (xi N) - d / tau (no solve).
 These tests build (1)-(3) in numpy from the Hermite rows alone and check
-them against the oracle's rows and its collision, to rounding."""
+them against the oracle's rows and its collision, to rounding; the same for
+the nineteen rows of D3Q19."""
 import math
 
 import numpy as np
 import pytest
 
 import oracle as O
+from oracle import d3q19 as D
 
 S3 = math.sqrt(3.0)
 
@@ -107,4 +109,70 @@ def test_kernel_form_equals_the_oracle_collision(tau, one_tau, ux0, uy0):
         f = f + 1e-4 * rng.standard_normal(9)
         want = O.collide(p, f, site=site, step=step)
         got = kernel_form(f, tau, kT, O.site_gaussians(seed, site, step), one_tau)
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------------------ D3Q19
+# The same algebra with nineteen rows: four conserved (1, sqrt3 (v_a - u_a))
+# and fifteen relaxed (the D3Q19 generalisation of Sec. V).
+
+
+def schur_factor3(u):
+    m = D.basis()
+    vx, vy, vz, _ = D.velocities()
+    v = np.stack([vx, vy, vz]).astype(float)
+    g = D.equilibrium(1.0, *u)
+    cons = np.vstack([np.ones(19)] + [S3 * (v[a] - u[a]) for a in range(3)])
+    hm = m[4:]
+    G = hm @ np.diag(g) @ hm.T
+    P = cons @ np.diag(g) @ hm.T
+    return np.linalg.cholesky(G - P.T @ P)
+
+
+@pytest.mark.parametrize("u", [(0.0, 0.0, 0.0), (0.1, -0.05, 0.03), (0.2, 0.1, -0.15)])
+def test_d3q19_change_through_hermite_rows_equals_the_fnorm_sum(u):
+    m = D.basis()
+    w = D.velocities()[3]
+    mt = D.fnorm_basis(*u)
+    g = D.equilibrium(1.0, *u)
+    L = schur_factor3(u)
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        dM = rng.standard_normal(15)
+        df = (mt[4:] * g).T @ dM
+        assert np.abs(m[:4] @ df).max() < 1e-13
+        np.testing.assert_allclose(m[4:] @ df, L @ dM, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(df, w * (m[4:].T @ (L @ dM)), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("one_tau", [True, False])
+def test_d3q19_kernel_form_equals_the_oracle_collision(one_tau):
+    """The D3Q19 f-norm collision with noise in the kernels' form (Y seeded
+    with -d / tau and L (xi N) added for one relaxation time; L (xi N -
+    L^-1 d / tau) otherwise) against the oracle's collision."""
+    m = D.basis()
+    w = D.velocities()[3]
+    if one_tau:
+        tau = np.full(15, 0.8)
+    else:
+        tau = np.round(np.random.default_rng(2).uniform(0.6, 1.5, 15), 6)
+    kT, seed, u0 = 1e-3, 9, (0.1, -0.05, 0.03)
+    p = D.make_params(3, 3, 3, ux0=u0[0], uy0=u0[1], uz0=u0[2], kT=kT, tau=tuple(tau), seed=seed)
+    rng = np.random.default_rng(6)
+    for site, step in ((0, 0), (7, 2), (26, 999)):
+        f = D.equilibrium(1.0 + 0.01 * rng.standard_normal(),
+                          *(u0[a] + 0.01 * rng.standard_normal() for a in range(3)))
+        f = f + 1e-4 * rng.standard_normal(19)
+        want = D.collide(p, f, site=site, step=step)
+        rho = f.sum()
+        u = (m[1:4] @ f) / (S3 * rho)
+        d = m[4:] @ (f - D.equilibrium(rho, *u))
+        L = schur_factor3(u)
+        xi = np.sqrt(3.0 * kT * rho * (2.0 * tau - 1.0)) / tau
+        N = D.site_gaussians(seed, site, step)
+        if one_tau:
+            Y = -d / tau[0] + L @ (xi * N)
+        else:
+            Y = L @ (xi * N - np.linalg.solve(L, d) / tau)
+        got = f + w * (m[4:].T @ Y)
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
