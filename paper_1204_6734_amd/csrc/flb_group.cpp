@@ -35,6 +35,7 @@ void Group::layout(Arena& a) {
   d_open = a.take<double>(kNStat);
   d_B = a.take<double>(81);
   d_mode = a.take<double2>(kModeBlocks);
+  d_close = a.take<double*>(2 * (size_t)n);
   pop.resize(n);
   d_partials.assign(n, nullptr);
   d_records.assign(n, nullptr);
@@ -173,6 +174,12 @@ int Group::init(const flb_params* ps, int n, void* stream, void* dev_buf, size_t
       ctiles[c] = acc;
     }
     HIPC(hipMemcpy(d_slots, dev_desc.data(), n * sizeof(SlotDesc), hipMemcpyHostToDevice));
+    std::vector<double*> close(2 * (size_t)n);
+    for (int s = 0; s < n; ++s) {
+      close[s] = d_partials[s];
+      close[n + s] = d_records[s];
+    }
+    HIPC(hipMemcpy(d_close, close.data(), close.size() * sizeof(double*), hipMemcpyHostToDevice));
     HIPC(hipMemcpy(d_prefix, dev_prefix.data(), dev_prefix.size() * sizeof(int),
                    hipMemcpyHostToDevice));
   }
@@ -243,22 +250,45 @@ bool Group::sk_due(int s, uint64_t tt) const {
   return d_skacc && p.sk_every > 0 && tt % (uint64_t)p.sk_every == 0;
 }
 
+// Whether every slot closes a time block after the sample of time tt, all
+// at the same record index, with no record merge first and one tile count:
+// an ensemble whose replicas sample alike.  Then one batched launch closes
+// them all, each with the additions of its own close.
+bool Group::lockstep_close(uint64_t tt) const {
+  const int n = (int)P.size();
+  if (n < 2) return false;
+  for (int s = 0; s < n; ++s)
+    if (!sample_due(s, tt) || !stats[s].plain_close_next() || stats[s].nb != stats[0].nb ||
+        hdesc[s].ntiles != hdesc[0].ntiles)
+      return false;
+  return true;
+}
+
 // Work after the step kernel of time tt: structure-factor transform and
 // time-block bookkeeping.  After a graph replay the transforms of the
 // chunk's steps ran inside the graph (replayed = true): only the counts and
 // the time-block closes remain.
 int Group::after_step(uint64_t tt, bool replayed) {
-  for (int s = 0; s < (int)P.size(); ++s) {
+  const int n = (int)P.size();
+  for (int s = 0; s < n; ++s) {
     if (sk_due(s, tt)) {
       if (!replayed)
         HIPC(launch_sk_sample(storage, d_z, d_zt, d_skacc, P[s].nx, P[s].ny, d_twx, d_twy,
                               max_lds, st));
       nsk += 1;
     }
+  }
+  if (lockstep_close(tt)) {
+    uint64_t b = 0;
+    for (int s = 0; s < n; ++s) b = stats[s].close_counted((uint64_t)P[s].nx * P[s].ny);
+    HIPC(launch_close_block_many(d_close, d_close + n, (size_t)b * kNStat, n, hdesc[0].ntiles,
+                                 st));
+    return FLB_OK;
+  }
+  for (int s = 0; s < n; ++s)
     if (sample_due(s, tt))
       HIPC(stats[s].after_sample((uint64_t)P[s].nx * P[s].ny, d_partials[s], hdesc[s].ntiles,
                                  d_records[s], st));
-  }
   return FLB_OK;
 }
 

@@ -47,6 +47,7 @@ struct Group {
   int band_rows = 1;
   std::vector<void*> pop;
   std::vector<double*> d_partials, d_records;
+  double** d_close = nullptr;  // [2n] device copies: every slot's partials, then its records
   // structure factor: complex planes and twiddles in the storage precision
   void* d_z = nullptr;
   void* d_zt = nullptr;
@@ -81,6 +82,7 @@ struct Group {
   bool sample_due(int s, uint64_t tt) const;
   bool sk_due(int s, uint64_t tt) const;
   int after_step(uint64_t tt, bool replayed = false);
+  bool lockstep_close(uint64_t tt) const;
   int launch_one(uint32_t k, bool sample, int odd);
   hipError_t launch_classes(uint32_t k, bool sample, int odd, LaunchCfg c);
   bool graph_friendly() const;

@@ -562,6 +562,11 @@ hipError_t launch_close_block(double* partials, int ntiles, double* record, hipS
   return close_block_sums<kNStat>(partials, ntiles, record, st);
 }
 
+hipError_t launch_close_block_many(double* const* partials, double* const* records,
+                                  size_t record_offset, int n, int ntiles, hipStream_t st) {
+  return close_block_sums_many<kNStat>(partials, records, record_offset, n, ntiles, st);
+}
+
 hipError_t launch_merge_blocks(double* rec, int nhalf, hipStream_t st) {
   hipLaunchKernelGGL(merge_blocks_kernel, dim3(1), dim3(64), 0, st, rec, nhalf);
   return hipGetLastError();

@@ -21,8 +21,7 @@ struct SumShape {
 // (lane j takes every J-th tile, then the J lane sums are added in order),
 // writes the sum into the range's first row and clears the others.
 template <int NSTAT>
-__global__ __launch_bounds__(1024) void fold_tiles_kernel(double* partials, int ntiles,
-                                                          int chunk) {
+__device__ __forceinline__ void fold_tiles(double* partials, int ntiles, int chunk) {
   constexpr int VP = SumShape<NSTAT>::VP, J = SumShape<NSTAT>::J;
   __shared__ double red[J][VP];
   const int v = threadIdx.x % VP, j = threadIdx.x / VP;
@@ -47,7 +46,8 @@ __global__ __launch_bounds__(1024) void fold_tiles_kernel(double* partials, int 
 
 // Stage two: record = the folded rows summed in range order; rows cleared.
 template <int NSTAT>
-__global__ void gather_folds_kernel(double* partials, int nranges, int chunk, double* record) {
+__device__ __forceinline__ void gather_folds(double* partials, int nranges, int chunk,
+                                             double* record) {
   const int v = threadIdx.x;
   if (v >= NSTAT) return;
   double s = 0.0;
@@ -57,6 +57,31 @@ __global__ void gather_folds_kernel(double* partials, int nranges, int chunk, do
     *q = 0.0;
   }
   record[v] = s;
+}
+
+template <int NSTAT>
+__global__ __launch_bounds__(1024) void fold_tiles_kernel(double* partials, int ntiles,
+                                                          int chunk) {
+  fold_tiles<NSTAT>(partials, ntiles, chunk);
+}
+
+template <int NSTAT>
+__global__ void gather_folds_kernel(double* partials, int nranges, int chunk, double* record) {
+  gather_folds<NSTAT>(partials, nranges, chunk, record);
+}
+
+// The same two stages for several lattices of one tile count at once, the
+// lattice in blockIdx.y: each one's sums are added in the order above.
+template <int NSTAT>
+__global__ __launch_bounds__(1024) void fold_tiles_many_kernel(double* const* partials, int ntiles,
+                                                               int chunk) {
+  fold_tiles<NSTAT>(partials[blockIdx.y], ntiles, chunk);
+}
+
+template <int NSTAT>
+__global__ void gather_folds_many_kernel(double* const* partials, int nranges, int chunk,
+                                         double* const* records, size_t record_offset) {
+  gather_folds<NSTAT>(partials[blockIdx.y], nranges, chunk, records[blockIdx.y] + record_offset);
 }
 
 // Open sums (partials left as they are): one workgroup, lanes as above.
@@ -98,6 +123,24 @@ hipError_t close_block_sums(double* partials, int ntiles, double* record, hipStr
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gather_folds_kernel<NSTAT>, dim3(1), dim3(SumShape<NSTAT>::VP), 0, st,
                      partials, nranges, chunk, record);
+  return hipGetLastError();
+}
+
+// For n lattices of ntiles tiles each (device arrays of their partials and
+// record bases): records[k] + record_offset = lattice k's sums; its
+// partials cleared.  The same sums as close_block_sums for each.
+template <int NSTAT>
+hipError_t close_block_sums_many(double* const* partials, double* const* records,
+                                 size_t record_offset, int n, int ntiles, hipStream_t st) {
+  if (ntiles <= 0 || n <= 0) return hipErrorInvalidValue;
+  int chunk = 1, nranges = 1;
+  fold_ranges(ntiles, &chunk, &nranges);
+  hipLaunchKernelGGL(fold_tiles_many_kernel<NSTAT>, dim3(nranges, n), dim3(1024), 0, st,
+                     partials, ntiles, chunk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gather_folds_many_kernel<NSTAT>, dim3(1, n), dim3(SumShape<NSTAT>::VP), 0,
+                     st, partials, nranges, chunk, records, record_offset);
   return hipGetLastError();
 }
 

@@ -255,6 +255,20 @@ hipError_t Stats::after_sample(uint64_t nsites, double* d_partials, int ntiles, 
   return e;
 }
 
+bool Stats::plain_close_next() const {
+  return tb_len != 0 && tb_fill + 1 == tb_len && nb < (uint64_t)max_blocks;
+}
+
+uint64_t Stats::close_counted(uint64_t nsites) {
+  nsamples += nsites;
+  if (rec_len.size() < (size_t)max_blocks) rec_len.assign(max_blocks, 0);
+  const uint64_t b = nb;
+  rec_len[b] = tb_fill + 1;
+  nb += 1;
+  tb_fill = 0;
+  return b;
+}
+
 uint64_t Stats::block_samples(uint64_t b) const { return b < rec_len.size() ? rec_len[b] : 0; }
 
 static void cov_from(const double* S, double n, double C[81]) {

@@ -39,6 +39,11 @@ struct Stats {
   void reset(int block_steps);
   hipError_t after_sample(uint64_t nsites, double* d_partials, int ntiles, double* d_records,
                           hipStream_t st);
+  // Whether the next sample closes a time block without first merging
+  // records; then close_counted does that sample's bookkeeping and returns
+  // the record index, and the caller closes the block on the device.
+  bool plain_close_next() const;
+  uint64_t close_counted(uint64_t nsites);
   uint64_t block_samples(uint64_t b) const;
 };
 
@@ -69,6 +74,10 @@ hipError_t launch_fourier_mode(int storage, const void* pop, uint32_t P, double2
                                int nx, int ny, int odd, int which, int kx, int ky, double rho0,
                                double ux0, double uy0, hipStream_t st);
 hipError_t launch_close_block(double* partials, int ntiles, double* record, hipStream_t st);
+// n lattices of ntiles tiles each at once (device arrays of their partials
+// and record bases; the record written at records[k] + record_offset)
+hipError_t launch_close_block_many(double* const* partials, double* const* records,
+                                  size_t record_offset, int n, int ntiles, hipStream_t st);
 hipError_t launch_merge_blocks(double* rec, int nhalf, hipStream_t st);
 hipError_t launch_open_sum(const double* partials, int ntiles, double* out, hipStream_t st);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
