@@ -32,6 +32,33 @@ def test_ensemble_replicas_equal_alone(flb, chunk):
         np.testing.assert_array_equal(ce["se_cov_f"], cl["se_cov_f"])
 
 
+def test_ensemble_block_closes_in_and_out_of_step_equal_alone(flb):
+    """Replicas that close their time blocks together are closed by one
+    batched launch; replicas whose blocks or sampling differ, and closes that
+    first merge full record lists, take one launch each.  Mixed ensembles
+    (every replica closing each sample, with merges of the records; and
+    block lengths 3, 3 and 5 with sampling every 1, 1 and 2) against the
+    same lattices alone: correlator sums, standard errors and block counts
+    bit for bit."""
+    cases = [[dict(sample_every=1, block_steps=1)] * 3,
+             [dict(sample_every=1, block_steps=3), dict(sample_every=1, block_steps=3),
+              dict(sample_every=2, block_steps=5)]]
+    for steps, extras in ((1100, cases[0]), (97, cases[1])):
+        ps = [flb.make_params(16, 8, precision=flb.FP32_SHIFTED, ux0=0.05 * k, kT=1e-4,
+                              seed=500 + k, **e) for k, e in enumerate(extras)]
+        E = flb.Ensemble(ps, graph_chunk=0)
+        E.step(steps)
+        for i, p in enumerate(ps):
+            L = flb.Lattice(p)
+            L.step(steps)
+            ce, cl = E.covariance(i), L.covariance()
+            assert ce["nblocks"] == cl["nblocks"] and ce["nsamples"] == cl["nsamples"]
+            for k in ("mean_df", "cov_f", "se_cov_f", "se_cov_m"):
+                np.testing.assert_array_equal(ce[k], cl[k], err_msg=f"replica {i} {k}")
+            L.close()
+        E.close()
+
+
 def test_ensemble_graph_replay_equals_eager(flb):
     ps = members(flb, 4, 128, 128, flb.FP32_SHIFTED, sample_every=1, block_steps=40)
     a = flb.Ensemble(ps, graph_chunk=20)
