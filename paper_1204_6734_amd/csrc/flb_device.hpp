@@ -56,7 +56,7 @@ __device__ __forceinline__ uint4 philox4x32_10_site(uint32_t site, uint32_t c1, 
                                                    uint32_t c3, uint32_t k0, uint32_t k1) {
   constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
   constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-  // round 1 on (site, c1, c2, c3)
+  // first Philox round, on (site, c1, c2, c3)
   uint64_t p0 = (uint64_t)M0 * (uint64_t)site;
   uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
   const uint32_t x1 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;        // uniform
@@ -65,7 +65,7 @@ __device__ __forceinline__ uint4 philox4x32_10_site(uint32_t site, uint32_t c1, 
   const uint32_t w1 = (uint32_t)p0;                          // per lane
   k0 += W0;
   k1 += W1;
-  // round 2 on (x1, y1, z1, w1)
+  // second Philox round, on (x1, y1, z1, w1)
   p0 = (uint64_t)M0 * (uint64_t)x1;                          // uniform
   p1 = (uint64_t)M1 * (uint64_t)z1;
   uint4 c = make_uint4((uint32_t)(p1 >> 32) ^ (y1 ^ k0), (uint32_t)p1,
