@@ -53,9 +53,14 @@ D3Q19_VALU_PER_SITE = 2095
 # cos) 1 each (48); conversions, compares and min/max are not counted.  One
 # lane computes one site.
 D3Q19_FLOPS_PER_SITE = 3396
+# the same for the FP64 kernel of that workload: 1804 FMAs, 327 multiplies,
+# 117 adds and subtracts, 33 transcendentals (FP64 operations)
+D3Q19_FP64_FLOPS_PER_SITE = 4085
 # FP32 vector peak without packed (two-wide) instructions, which this
-# library does not use: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+# library does not use: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz;
+# the FP64 vector peak is the same
 FP32_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9
+FP64_VECTOR_PEAK = FP32_VECTOR_PEAK
 # VALU issue peak: 256 CUs x 4 SIMDs, one wavefront instruction (64 lanes,
 # 16 per cycle) every 4 cycles at 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
@@ -387,10 +392,13 @@ def run_serving(F, torch, nreq: int = 40, rate: float = 50.0, chunk: int = 100,
     return out
 
 
-def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256):
-    """The D3Q19 generalisation: an n^3 FP32-shifted lattice in the local
-    f-norm basis (u0 = (0.1, 0, 0), kT = 1e-4, tau = 1), no sampling."""
-    p = F.make_params3(n, n, n, precision=F.FP32_SHIFTED, ux0=0.1, kT=1e-4, seed=1)
+def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256, precision: str = "fp32"):
+    """The D3Q19 generalisation: an n^3 lattice, FP32-shifted (or FP64)
+    storage, in the local f-norm basis (u0 = (0.1, 0, 0), kT = 1e-4, tau =
+    1), no sampling."""
+    fp64 = precision == "fp64"
+    p = F.make_params3(n, n, n, precision=F.FP64 if fp64 else F.FP32_SHIFTED, ux0=0.1,
+                       kT=1e-4, seed=1)
     L = F.Lattice3(p, stream=torch.cuda.current_stream())
     L.step(warmup)
     L.sync()
@@ -403,25 +411,30 @@ def run_d3q19(F, torch, steps: int, warmup: int, n: int = 256):
     kms, launches = L.kernel_time()
     sites = n ** 3
     kernel_ms = kms / max(launches, 1)
-    achieved = 152 * sites / (kernel_ms * 1e-3) / 1e9
-    # the kernel is bound by its vector arithmetic: FP32 flops per site (from
-    # its code) against the unpacked FP32 vector peak; beside it the HBM
-    # fraction of its 152 algorithmic bytes per site, and its VALU issue
-    # (wavefront instructions per site from the SQ_INSTS_VALU counter)
-    tflops = D3Q19_FLOPS_PER_SITE * sites / (kernel_ms * 1e-3) / 1e12
-    wave_instr = D3Q19_VALU_PER_SITE * sites / 64
-    return {"mlups": sites * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps,
-            "kernel_ms": kernel_ms, "sites": sites, "steps": steps,
-            "roofline": {"bound": "alu", "achieved": round(tflops, 2),
-                         "peak": round(FP32_VECTOR_PEAK / 1e12, 1), "unit": "TFLOP/s",
-                         "frac": round(tflops * 1e12 / FP32_VECTOR_PEAK, 4),
-                         "flops_per_site": D3Q19_FLOPS_PER_SITE,
-                         "kernel": "step3_kernel<float,float,fnorm>"},
-            "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_site": 152},
-            "valu_issue": {"wavefront_instructions_per_site": D3Q19_VALU_PER_SITE,
-                           "issue_ms_at_4_cycles": round(wave_instr / VALU_ISSUE_PEAK * 1e3,
-                                                         4)}}
+    bytes_per_site = 304 if fp64 else 152
+    achieved = bytes_per_site * sites / (kernel_ms * 1e-3) / 1e9
+    # the kernel is bound by its vector arithmetic: flops per site (from its
+    # code) against the vector peak without packed instructions; beside it
+    # the HBM fraction of its algorithmic bytes per site, and (FP32) its VALU
+    # issue (wavefront instructions per site from the SQ_INSTS_VALU counter)
+    flops = D3Q19_FP64_FLOPS_PER_SITE if fp64 else D3Q19_FLOPS_PER_SITE
+    peak = FP64_VECTOR_PEAK if fp64 else FP32_VECTOR_PEAK
+    tflops = flops * sites / (kernel_ms * 1e-3) / 1e12
+    out = {"mlups": sites * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps,
+           "kernel_ms": kernel_ms, "sites": sites, "steps": steps,
+           "roofline": {"bound": "alu", "achieved": round(tflops, 2),
+                        "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
+                        "frac": round(tflops * 1e12 / peak, 4), "flops_per_site": flops,
+                        "kernel": "step3_kernel<%s,fnorm>" % ("double,double" if fp64 else
+                                                              "float,float")},
+           "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_site": bytes_per_site}}
+    if not fp64:
+        wave_instr = D3Q19_VALU_PER_SITE * sites / 64
+        out["valu_issue"] = {"wavefront_instructions_per_site": D3Q19_VALU_PER_SITE,
+                             "issue_ms_at_4_cycles": round(wave_instr / VALU_ISSUE_PEAK * 1e3,
+                                                           4)}
+    return out
 
 
 def run_config2(F) -> dict:
@@ -516,9 +529,10 @@ def main():
         print(json.dumps({"workload": "64 x 128^2 FP32 ensemble, hipGraph", **r}), flush=True)
         return
     if args.workload == "d3q19":
-        r = run_d3q19(F, torch, args.steps, args.warmup)
-        print(json.dumps({"workload": "256^3 D3Q19 FP32-shifted, f-norm, u_x0=0.1, kT=1e-4, "
-                                      "tau=1", **r}), flush=True)
+        r = run_d3q19(F, torch, args.steps, args.warmup, precision=args.precision)
+        store = "FP64" if args.precision == "fp64" else "FP32-shifted"
+        print(json.dumps({"workload": f"256^3 D3Q19 {store}, f-norm, u_x0=0.1, kT=1e-4, tau=1",
+                          **r}), flush=True)
         return
     if args.workload == "paper":
         from paper_1204_6734_amd import analysis as A
