@@ -458,8 +458,9 @@ __device__ __forceinline__ uint32_t cell(int x, int y, int z, const Desc3& d) {
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 // Wavefronts per SIMD the register allocation of a step variant aims at:
-// three in FP32 (the f-norm collision then spills 32-40 bytes per lane and
-// still runs 1.5 % faster than at two), one in FP64.
+// three in FP32 (the one-relaxation-time f-norm collision fits in 163
+// registers; the general one spills 32-40 bytes per lane there and still
+// runs 1.5 % faster than at two), one in FP64.
 template <typename R>
 constexpr int waves3() {
   return sizeof(R) == 8 ? 1 : 3;
