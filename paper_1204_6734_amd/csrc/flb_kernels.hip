@@ -425,14 +425,23 @@ __global__ void dft_rows_kernel(const typename Cplx<T>::type* __restrict__ in,
 }
 
 // out[c][r] = in[r][c] for gridDim.z matrices of rows x cols complex values,
-// through TILE x TILE tiles in LDS (256 threads; 32 for double2, 64 for
-// float2, 16 KB or 32 KB of LDS).
+// through 32 x 32 tiles in LDS (256 threads, 8 or 16 KB of LDS: more
+// workgroups per CU than with 64 x 64 tiles).  The tiles are taken in
+// diagonal order: block b of a matrix takes tile row b mod gy and tile column
+// (b / gy + b mod gy) mod gx (a bijection of the gx x gy grid), so blocks
+// that run together read and write segments of different rows and columns
+// rather than all at one offset of the power-of-two row stride.
+constexpr int kTransposeTile = 32;
+
 template <typename V>
 __global__ __launch_bounds__(256) void transpose_kernel(const V* __restrict__ in, V* out,
                                                         int rows, int cols) {
-  constexpr int TILE = sizeof(V) == 16 ? 32 : 64, STEP = 256 / TILE;
+  constexpr int TILE = kTransposeTile, STEP = 256 / TILE;
   __shared__ V tile[TILE][TILE + 1];
-  const int bx = blockIdx.x * TILE, by = blockIdx.y * TILE;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int b = blockIdx.y * gx + blockIdx.x;
+  const int tr = b % gy, tc = (b / gy + tr) % gx;
+  const int bx = tc * TILE, by = tr * TILE;
   const size_t z = blockIdx.z;
   const V* src = in + z * (size_t)rows * cols;
   V* dst = out + z * (size_t)rows * cols;
@@ -664,7 +673,7 @@ static hipError_t sk_sample_t(void* z, void* zt, double* acc, int nx, int ny, co
   V* b = (V*)zt;
   hipError_t e = row_transform<T>(a, b, nx, 2 * ny, (const V*)twx, max_lds, st);
   if (e != hipSuccess) return e;
-  constexpr int TILE = sizeof(V) == 16 ? 32 : 64;
+  constexpr int TILE = kTransposeTile;
   hipLaunchKernelGGL(transpose_kernel<V>, dim3((nx + TILE - 1) / TILE, (ny + TILE - 1) / TILE, 2),
                      dim3(256), 0, st, b, a, ny, nx);
   e = row_transform<T>(a, b, ny, 2 * nx, (const V*)twy, max_lds, st);
