@@ -611,10 +611,12 @@ int Group::read_fourier_mode(int which, int kx, int ky, double out[2]) {
   if (which < 0 || which > 2) return set_error(FLB_E_ARG, "unknown field %d", which);
   const flb_params& p = P[0];
   const int nkx = ((kx % p.nx) + p.nx) % p.nx, nky = ((ky % p.ny) + p.ny) % p.ny;
-  HIPC(launch_fourier_mode(storage, pop[0], hdesc[0].pitch, d_mode, kModeBlocks, p.nx, p.ny, (int)(t & 1), which,
-                           nkx, nky, p.rho0, p.ux0, p.uy0, st));
-  std::vector<double2> part(kModeBlocks);
-  HIPC(hipMemcpyAsync(part.data(), d_mode, kModeBlocks * sizeof(double2), hipMemcpyDeviceToHost,
+  int gx, gy;
+  const int nblocks = fourier_mode_grid(p.nx, p.ny, kModeBlocks, &gx, &gy);
+  HIPC(launch_fourier_mode(storage, pop[0], hdesc[0].pitch, d_mode, kModeBlocks, p.nx, p.ny,
+                           (int)(t & 1), which, nkx, nky, p.ux0, p.uy0, st));
+  std::vector<double2> part(nblocks);
+  HIPC(hipMemcpyAsync(part.data(), d_mode, nblocks * sizeof(double2), hipMemcpyDeviceToHost,
                       st));
   HIPC(hipStreamSynchronize(st));
   double sr = 0, si = 0;

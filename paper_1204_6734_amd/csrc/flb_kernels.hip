@@ -169,31 +169,47 @@ __global__ void moments_kernel(const S* __restrict__ pop, uint32_t P,
 }
 
 // Partial sums of one Fourier coefficient sum_x dA(x) e^{-i k.x} per block.
+// A thread holds one column x at a time (256 consecutive columns per block,
+// so the loads of a row are coalesced) and walks the rows y = blockIdx.y,
+// blockIdx.y + gridDim.y, ...; e^{-i k.x} = e^{-2 pi i kx x / nx}
+// e^{-2 pi i ky y / ny}, so the column's factor is evaluated once per column
+// and the row's once per row (not at all for ky = 0).
 template <typename S>
-__global__ void fourier_mode_kernel(const S* __restrict__ pop, uint32_t P, double2* partial,
-                                    int nx, int ny, int odd, int which, int kx, int ky,
-                                    double rho0, double ux0, double uy0) {
+__global__ __launch_bounds__(256) void fourier_mode_kernel(const S* __restrict__ pop, uint32_t P,
+                                                           double2* partial, int nx, int ny,
+                                                           int odd, int which, int kx, int ky,
+                                                           double ux0, double uy0) {
   __shared__ double sr[256], si[256];
   const int tid = threadIdx.x;
-  const uint32_t N = (uint32_t)nx * ny;
   double ar = 0.0, ai = 0.0;
-  for (uint32_t site = blockIdx.x * 256u + tid; site < N; site += gridDim.x * 256u) {
-    const int y = (int)(site / (uint32_t)nx), x = (int)(site - (uint32_t)y * nx);
-    uint32_t idx[9];
-    site_indices(x, y, nx, ny, odd, P, idx);
-    double h[9];
-    for (int i = 0; i < 9; ++i) h[i] = (double)pop[idx[i]];
-    const Moments<double> m = hermite_moments(h);
-    double a = m.drho;
-    if (which == 1) a = 1.7320508075688772935 * (m.jx - ux0 * m.drho);
-    if (which == 2) a = 1.7320508075688772935 * (m.jy - uy0 * m.drho);
-    (void)rho0;
-    const long long px = ((long long)kx * x) % nx, py = ((long long)ky * y) % ny;
-    const double ph = 2.0 * ((double)px / nx + (double)py / ny);
+  for (int x = blockIdx.x * 256 + tid; x < nx; x += gridDim.x * 256) {
+    double cr = 0.0, ci = 0.0;  // sum over this thread's rows of dA e^{-i phi_y}
+    for (int y = blockIdx.y; y < ny; y += gridDim.y) {
+      uint32_t idx[9];
+      site_indices(x, y, nx, ny, odd, P, idx);
+      double h[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) h[i] = (double)pop[idx[i]];
+      const Moments<double> m = hermite_moments(h);
+      double a = m.drho;
+      if (which == 1) a = 1.7320508075688772935 * (m.jx - ux0 * m.drho);
+      if (which == 2) a = 1.7320508075688772935 * (m.jy - uy0 * m.drho);
+      if (ky == 0) {
+        cr += a;
+      } else {
+        const long long py = ((long long)ky * y) % ny;
+        double sn, cs;
+        sincospi(2.0 * ((double)py / ny), &sn, &cs);
+        cr += a * cs;
+        ci -= a * sn;
+      }
+    }
+    const long long px = ((long long)kx * x) % nx;
     double sn, cs;
-    sincospi(ph, &sn, &cs);
-    ar += a * cs;
-    ai -= a * sn;
+    sincospi(2.0 * ((double)px / nx), &sn, &cs);
+    // (cr + i ci) (cs - i sn)
+    ar += cr * cs + ci * sn;
+    ai += ci * cs - cr * sn;
   }
   sr[tid] = ar;
   si[tid] = ai;
@@ -205,7 +221,7 @@ __global__ void fourier_mode_kernel(const S* __restrict__ pop, uint32_t P, doubl
     }
     __syncthreads();
   }
-  if (tid == 0) partial[blockIdx.x] = make_double2(sr[0], si[0]);
+  if (tid == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = make_double2(sr[0], si[0]);
 }
 
 // ------------------------------------------------------------ time blocks
@@ -552,18 +568,26 @@ hipError_t launch_moments(int storage, const void* pop, uint32_t P, const double
   return hipGetLastError();
 }
 
+int fourier_mode_grid(int nx, int ny, int max_blocks, int* gx, int* gy) {
+  const int cols = (nx + 255) / 256;
+  *gx = cols < max_blocks ? cols : max_blocks;
+  const int rows = max_blocks / *gx;
+  *gy = rows < 1 ? 1 : (rows < ny ? rows : ny);
+  return *gx * *gy;
+}
+
 hipError_t launch_fourier_mode(int storage, const void* pop, uint32_t P, double2* partial,
-                               int nblocks,
-                               int nx, int ny, int odd, int which, int kx, int ky, double rho0,
+                               int max_blocks, int nx, int ny, int odd, int which, int kx, int ky,
                                double ux0, double uy0, hipStream_t st) {
+  int gx, gy;
+  fourier_mode_grid(nx, ny, max_blocks, &gx, &gy);
+  const dim3 grid(gx, gy);
   if (storage == 0)
-    hipLaunchKernelGGL(fourier_mode_kernel<double>, dim3(nblocks), dim3(256), 0, st,
-                       (const double*)pop, P, partial, nx, ny, odd, which, kx, ky, rho0, ux0,
-                       uy0);
+    hipLaunchKernelGGL(fourier_mode_kernel<double>, grid, dim3(256), 0, st, (const double*)pop, P,
+                       partial, nx, ny, odd, which, kx, ky, ux0, uy0);
   else
-    hipLaunchKernelGGL(fourier_mode_kernel<float>, dim3(nblocks), dim3(256), 0, st,
-                       (const float*)pop, P, partial, nx, ny, odd, which, kx, ky, rho0, ux0,
-                       uy0);
+    hipLaunchKernelGGL(fourier_mode_kernel<float>, grid, dim3(256), 0, st, (const float*)pop, P,
+                       partial, nx, ny, odd, which, kx, ky, ux0, uy0);
   return hipGetLastError();
 }
 

@@ -69,9 +69,12 @@ hipError_t launch_init(int storage, void* pop, uint32_t P, const double* rho, co
 hipError_t launch_moments(int storage, const void* pop, uint32_t P, const double* B, double* out,
                           int nx, int ny, int odd, double rho0, double ux0, double uy0,
                           const Shift9& sh, int* err, int y0, int rows, hipStream_t st);
+// The Fourier-coefficient readback: a grid of gx blocks of 256 columns by
+// gy row groups, gx * gy <= max_blocks (returned), one partial per block
+// at blockIdx.y * gx + blockIdx.x.
+int fourier_mode_grid(int nx, int ny, int max_blocks, int* gx, int* gy);
 hipError_t launch_fourier_mode(int storage, const void* pop, uint32_t P, double2* partial,
-                               int nblocks,
-                               int nx, int ny, int odd, int which, int kx, int ky, double rho0,
+                               int max_blocks, int nx, int ny, int odd, int which, int kx, int ky,
                                double ux0, double uy0, hipStream_t st);
 hipError_t launch_close_block(double* partials, int ntiles, double* record, hipStream_t st);
 // n lattices of ntiles tiles each at once (device arrays of their partials

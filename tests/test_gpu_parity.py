@@ -336,6 +336,31 @@ def test_fourier_mode_matches_oracle(flb):
         assert abs(a - b) <= 1e-12 * max(1e-3, abs(b)) * nx * ny
 
 
+@pytest.mark.parametrize("prec,nx,ny", [("fp64", 48, 10), ("fp64", 300, 7), ("fp32", 300, 7),
+                                         ("fp32", 8192, 8), ("fp64", 262500, 3)])
+def test_fourier_mode_of_the_gpu_state(flb, prec, nx, ny):
+    """The readback of one Fourier coefficient of d rho, dj~_x, dj~_y against
+    the oracle's coefficient (the separable sum by its definition) of the
+    GPU's own populations, at both streaming phases: one partly filled block
+    of 256 columns, two with a ragged second, the benchmark's row length, and
+    more column blocks than the readback has partials (a thread then walks
+    several columns); ky = 0 and ky != 0."""
+    ux0, uy0 = 0.1, -0.05
+    precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
+    g = flb.Lattice(flb.make_params(nx, ny, precision=precision, ux0=ux0, uy0=uy0, kT=1e-4,
+                                    seed=5, init=2))
+    g.set_fields(*I.random_fields(nx, ny, seed=3, ux0=ux0, uy0=uy0))
+    modes = [(2, 1, 0), (0, 3, 2), (1, nx - 1, ny - 1), (2, 0, 0), (1, nx // 2, 1)]
+    for _ in range(2):  # odd phase, then even phase
+        g.step(1)
+        fields = O.sk_fields(g.populations(), 1.0, ux0, uy0)
+        for which, kx, ky in modes:
+            a = g.fourier_mode(which, kx, ky)
+            b = O.fourier_coefficient(fields[which], kx, ky)
+            scale = np.abs(fields[which]).sum()
+            assert abs(a - b) <= 1e-12 * scale, (prec, nx, ny, g.t, which, kx, ky, a, b)
+
+
 def test_thermal_start_matches_oracle(flb):
     kw = dict(ux0=0.05, kT=1e-3, seed=21, init=1)
     g, o = both(flb, 20, 12, flb.FP64, **kw)
