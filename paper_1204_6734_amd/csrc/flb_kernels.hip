@@ -320,6 +320,25 @@ __device__ __forceinline__ float2 twiddle(const float2* __restrict__, int k, int
   return float2{__builtin_amdgcn_cosf(a), -__builtin_amdgcn_sinf(a)};
 }
 
+// w^(r step) for the r-th input of a butterfly, w1 = w^step.  FP64 reads
+// the table; FP32 takes products of w1 (w^2 = w1 w1, w^3 = w^2 w1, ...):
+// one sine and cosine per butterfly instead of one per input, each power
+// within a few FP32 roundings of the exact value.
+template <typename V>
+__device__ __forceinline__ V twiddle_pow(const V* __restrict__ tw, int step, int r, int n, V w1);
+template <>
+__device__ __forceinline__ double2 twiddle_pow<double2>(const double2* __restrict__ tw, int step,
+                                                        int r, int, double2) {
+  return tw[r * step];
+}
+template <>
+__device__ __forceinline__ float2 twiddle_pow<float2>(const float2* __restrict__, int, int r, int,
+                                                      float2 w1) {
+  float2 w = w1;
+  for (int q = 1; q < r; ++q) w = cmul(w, w1);
+  return w;
+}
+
 template <int R, int E, typename V>
 __device__ __forceinline__ void pass_compute(V (&a)[E], int n, int t, int Ns,
                                              const V* __restrict__ tw) {
@@ -329,8 +348,9 @@ __device__ __forceinline__ void pass_compute(V (&a)[E], int n, int t, int Ns,
     if (Ns > 1) {
       const int j = t + m * tpr;
       const int step = (j & (Ns - 1)) * (n / (Ns * R));
+      const V w1 = twiddle(tw, step, n);
 #pragma unroll
-      for (int r = 1; r < R; ++r) a[m * R + r] = cmul(a[m * R + r], twiddle(tw, r * step, n));
+      for (int r = 1; r < R; ++r) a[m * R + r] = cmul(a[m * R + r], twiddle_pow<V>(tw, step, r, n, w1));
     }
     dft<R>(&a[m * R]);
   }
