@@ -306,11 +306,15 @@ def test_time_block_merge_matches_oracle(flb):
 
 @pytest.mark.parametrize("prec,nx,ny", [("fp64", 16, 8), ("fp64", 12, 10), ("fp64", 64, 32),
                                          ("fp64", 8, 1024), ("fp32", 64, 32), ("fp32", 12, 10),
-                                         ("fp32", 256, 16)])
+                                         ("fp32", 256, 16), ("fp32", 96, 40), ("fp64", 40, 96),
+                                         ("fp32", 128, 64)])
 def test_structure_factor_matches_oracle(flb, prec, nx, ny):
     """S(k) of all five kinds against the oracle: FFT sizes from 8 to 1024
     (radix-8 passes after a radix-2 or -4 one), direct DFTs for other
-    sizes.  FP32-shifted lattices transform in FP32 (accumulators FP64)."""
+    sizes; transposes of several 32 x 32 tiles both ways, unequal in number
+    and ragged at the far edges (96 x 40, 40 x 96, 128 x 64), which the
+    diagonal tile order visits once each.  FP32-shifted lattices transform
+    in FP32 (accumulators FP64)."""
     precision = flb.FP64 if prec == "fp64" else flb.FP32_SHIFTED
     tol = 1e-10 if prec == "fp64" else 2e-5
     kw = dict(ux0=0.1, kT=1e-4, seed=9, sk_every=3)
